@@ -1,0 +1,89 @@
+"""CPU oracle for the one-sided hyperbolic (J-)Jacobi eigensolver.
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, ``__graft_entry__.smoke()`` and
+the ``cpu_baseline`` leg of ``bench.py`` may import this package.  The product
+library (``paper_1008_4166_amd``) never imports, links or calls it.
+
+The oracle is a plain non-blocked row-cyclic one-sided J-Jacobi written in C
+(``jj_oracle_body.inc``), instantiated for real/complex input in double and in
+long double (x87, 64-bit mantissa) working precision.  See the header of that
+file for the paper passages it follows and the readings taken where the printed
+Algorithm 3.1 is garbled.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libjjoracle.so")
+_SRC = [os.path.join(_HERE, "jj_oracle.c"), os.path.join(_HERE, "jj_oracle_body.inc")]
+CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-shared", "-fPIC"]
+
+
+def build(out=_SO, src_dir=_HERE, extra_flags=()):
+    """Compile the oracle with gcc (no FMA contraction, no reassociation)."""
+    cmd = ["gcc", *CFLAGS, *extra_flags, "-o", out, os.path.join(src_dir, "jj_oracle.c"), "-lm"]
+    subprocess.check_call(cmd)
+    return out
+
+
+_lib_cache = {}
+
+
+def load(path=_SO):
+    if path in _lib_cache:
+        return _lib_cache[path]
+    if not os.path.exists(path):
+        build(path)
+    lib = ctypes.CDLL(path)
+    for sfx, rt, st in (("d", ctypes.c_double, ctypes.c_double),
+                        ("ld", ctypes.c_longdouble, ctypes.c_longdouble),
+                        ("z", ctypes.c_double, ctypes.c_double),
+                        ("lz", ctypes.c_longdouble, ctypes.c_longdouble)):
+        f = getattr(lib, "jjo_solve_" + sfx)
+        f.restype = ctypes.c_int
+        f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                      ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                      ctypes.c_void_p, ctypes.c_void_p]
+    _lib_cache[path] = lib
+    return lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def solve(G, J, tol=0.0, max_sweeps=0, precision="double", vectors=True, final_G=False, lib=None):
+    """Eigenpairs of H = G J G^* by the oracle.
+
+    G: (n, n) float64 or complex128 array (any memory order; copied to
+    column-major).  J: n signs.  precision: "double" or "long" (long double
+    working precision).  Returns a dict with ``lam`` (sorted descending; float64
+    or longdouble), ``V`` (columns are unit eigenvectors, or None), ``status``,
+    ``sweeps``, ``rotations``, ``order`` (input column of each eigenvalue) and,
+    if requested, ``G`` (final working matrix in working precision).
+    """
+    lib = lib or load()
+    G = np.asarray(G)
+    n = G.shape[0]
+    cplx = np.iscomplexobj(G)
+    Gf = np.asfortranarray(G, dtype=np.complex128 if cplx else np.float64)
+    Jc = np.ascontiguousarray(np.asarray(J), dtype=np.int8)
+    long = precision == "long"
+    sfx = ("l" if long else "") + ("z" if cplx else "d")
+    rdt = np.longdouble if long else np.float64
+    lam = np.zeros(max(n, 1), dtype=rdt)
+    V = np.zeros((n, n), dtype=np.complex128 if cplx else np.float64, order="F") if vectors else None
+    Gfin = None
+    if final_G:
+        Gfin = np.zeros((n, n), dtype=(np.clongdouble if long else np.complex128) if cplx else rdt, order="F")
+    order = np.zeros(max(n, 1), dtype=np.int32)
+    sweeps = ctypes.c_int(0)
+    rots = ctypes.c_longlong(0)
+    st = getattr(lib, "jjo_solve_" + sfx)(_ptr(Gf), _ptr(Jc), n, max(n, 1), float(tol), int(max_sweeps),
+                                           _ptr(lam), _ptr(V), _ptr(Gfin), _ptr(order),
+                                           ctypes.byref(sweeps), ctypes.byref(rots))
+    return dict(lam=lam[:n], V=V, status=st, sweeps=sweeps.value, rotations=rots.value,
+                order=order[:n], G=Gfin)
