@@ -1,0 +1,224 @@
+"""Benchmark: one step = one complete solve (all steps of the hot path: sign
+reordering and partition, block sweeps of Gram / pivot solve / update, and
+the eigenpair finalisation) of the n = 4096 real FP64 workload (J with 3000
+positive entries, |lambda| log-uniform in [1e-12, 1], G = Q diag(sqrt|lambda|) W).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+
+Prints one JSON line.  value = eigenpairs/s = n * K / (time of K solves), with
+every solve's input G already resident in HBM (one pristine device copy per
+solve, made before the timed region, because a solve overwrites G).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6  # MFMA and vector
+WORKLOAD = 3
+
+
+def algorithmic_work(prof, n, cplx):
+    """Algorithmic flops and HBM bytes per launch of each kernel kind.
+
+    Gram, per pair of m columns: the Hermitian m x m block costs n*m*(m+1)
+    real flops (half of the 2*n*m^2 of a full product) and reads n*m*s bytes.
+    Update, per pair whose W_P is not the identity: 2*n*m^2 flops, n*m*s read
+    plus n*m*s written.  (complex: flops x4, s = 16.)  Pivot solve: each inner
+    sweep forms three length-m dot products for all m(m-1)/2 pairs (6m flops
+    each, real) and each rotation updates two columns of R and of W_P (12m
+    flops); plus the Cholesky factorisation, m^3/3 flops."""
+    s = 16 if cplx else 8
+    cf = 4 if cplx else 1
+    m = 2 * prof["block_width"] if prof["nblocks"] >= 2 else n
+    out = {}
+    g = prof["gram"]
+    if g["launches"]:
+        units = g["units"] / g["launches"]
+        out["gram"] = dict(flops=cf * units * n * m * (m + 1), bytes=units * n * m * s, ms=g["ms"] / g["launches"])
+    u = prof["update"]
+    if u["launches"]:
+        units = u["units"] / u["launches"]
+        out["update"] = dict(flops=cf * units * 2 * n * m * m, bytes=units * 2 * n * m * s,
+                             ms=u["ms"] / u["launches"])
+    p = prof["pivot"]
+    if p["launches"]:
+        mm = prof["pivot_cols"] / max(1, p["units"])  # mean solved pivot size
+        dots = prof["inner_sweeps"] * mm * (mm - 1) / 2 * 6 * mm
+        rots = prof["rotations"] * 12 * mm
+        chol = prof["pivot_cols3"] / 3.0
+        out["pivot"] = dict(flops=cf * (dots + rots + chol) / p["launches"], bytes=0.0, ms=p["ms"] / p["launches"])
+    f = prof["final"]
+    if f["launches"]:
+        out["final"] = dict(flops=3.0 * n * n * cf, bytes=2.0 * n * n * s, ms=f["ms"] / f["launches"])
+    return out
+
+
+def roofline(prof, n, cplx):
+    work = algorithmic_work(prof, n, cplx)
+    kinds = {k: prof[k]["ms"] for k in ("gram", "pivot", "update", "final")}
+    dom = max(kinds, key=kinds.get)
+    w = work[dom]
+    if dom == "pivot":
+        # plain FP64 ALU work (no MFMA): 256 CUs x 64 FP64 FMA lanes x 2 flops x 2.4 GHz
+        ach = w["flops"] / (w["ms"] * 1e-3) / 1e12
+        r = dict(bound="alu", achieved=ach, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s")
+    else:
+        ai = w["flops"] / max(w["bytes"], 1.0)
+        if ai < PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9):
+            ach = w["bytes"] / (w["ms"] * 1e-3) / 1e9
+            r = dict(bound="hbm", achieved=ach, peak=PEAK_HBM_GBS, unit="GB/s")
+        else:
+            ach = w["flops"] / (w["ms"] * 1e-3) / 1e12
+            r = dict(bound="mfma", achieved=ach, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s")
+    r["frac"] = r["achieved"] / r["peak"]
+    r["traffic"] = None
+    r["kernel"] = dom
+    r["avg_launch_ms"] = w["ms"]
+    return r, work
+
+
+def cpu_baseline(n_full, sweeps_full):
+    """The oracle, single-threaded, on a bounded sample: one row-cyclic sweep on
+    the n = 2048 instance of the same workload law, scaled by n^3 to n = 4096 and
+    by the oracle's sweep count on the full input."""
+    import jjgen
+    import oracle
+    ns = 2048
+    G, J, _ = jjgen.config(WORKLOAD, n=ns)
+    t = time.perf_counter()
+    r = oracle.solve(G, J, max_sweeps=1, vectors=False)
+    dt = time.perf_counter() - t
+    t_full = dt * (n_full / ns) ** 3 * sweeps_full
+    return dict(value=n_full / t_full, unit="eigenpairs/s", cores=1, kind="oracle",
+                sample="one oracle sweep on the n=%d instance of the workload (%.1f s), scaled by (4096/%d)^3 "
+                       "and by the oracle's %d sweeps on the n=4096 input" % (ns, dt, ns, sweeps_full),
+                sweep_seconds_sample=dt, status_sample=r["status"])
+
+
+def stored_oracle(k):
+    path = os.path.join(ROOT, "tests", "golden", "config%d_lambda_double.txt" % k)
+    if not os.path.exists(path):
+        return None, None
+    sweeps = None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("# status"):
+                sweeps = int(line.split()[4])
+    return np.loadtxt(path), sweeps
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--block-width", type=int, default=32)
+    ap.add_argument("--inner-mode", type=int, default=0)
+    ap.add_argument("--no-profile", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the solver runs on a single MI355X; "
+              "multi-GPU runs are not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import jjgen
+    import paper_1008_4166_amd as jj
+
+    t = time.perf_counter()
+    G, J, lam_pres = jjgen.config(WORKLOAD)
+    gen_s = time.perf_counter() - t
+    n = G.shape[0]
+    dev = torch.device("cuda:0")
+    # G is Fortran-ordered: G.T is C-contiguous with the column-major bytes of G
+    pristine = torch.from_numpy(np.ascontiguousarray(G.T)).to(dev)
+    K, W = args.steps, args.warmup
+    work = [pristine.clone() for _ in range(K + W)]
+    lam = torch.empty(n, dtype=torch.float64, device=dev)
+    Vt = torch.empty((n, n), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream().cuda_stream
+    opts = jj.make_opts(stream=stream, block_width=args.block_width, inner_mode=args.inner_mode,
+                        profile=0 if args.no_profile else 1)
+    infos = []
+
+    def step(Gbuf):
+        info = jj.jj_info()
+        st = jj.jjacobi_solve_ex(jj.JJ_F64, Gbuf.data_ptr(), J, n, n, lam.data_ptr(), Vt.data_ptr(), n, 0.0, 0,
+                                 opts, info)
+        if st not in (0,):
+            raise RuntimeError("solve status %d (%s)" % (st, jj.jjacobi_status_string(st)))
+        infos.append(info.as_dict())
+        return jj.jjacobi_last_profile()
+
+    for i in range(W):
+        step(work[i])
+    torch.cuda.synchronize()
+    profs = []
+    t0 = time.perf_counter()
+    for i in range(K):
+        profs.append(step(work[W + i]))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dt = t1 - t0
+    ms_step = dt / K * 1e3
+    timed_infos = infos[W:]
+    sweeps = [i["sweeps"] for i in timed_infos]
+
+    # accuracy of the last timed solve
+    lam_h = lam.cpu().numpy()
+    ref, oracle_sweeps = stored_oracle(WORKLOAD)
+    acc = {"vs_prescribed_max_rel": float(np.max(np.abs(lam_h - np.sort(lam_pres)[::-1]) / np.abs(np.sort(lam_pres)[::-1])))}
+    if ref is not None:
+        acc["vs_oracle_max_rel"] = float(np.max(np.abs(lam_h - ref) / np.abs(ref)))
+        acc["vs_oracle_p99_rel"] = float(np.percentile(np.abs(lam_h - ref) / np.abs(ref), 99))
+
+    out = {
+        "metric": "eigenpairs/s (n=4096 FP64 solve); sweep time, FP64-MFMA fraction reported alongside",
+        "value": n * K / dt,
+        "unit": "eigenpairs/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "blocked real symmetric indefinite n=4096 float64, J with 3000 positive, "
+                               "|lambda| log-uniform [1e-12, 1], plain FP64",
+                   "n": n, "block_width": timed_infos[-1]["block_width"], "nblocks": timed_infos[-1]["nblocks"],
+                   "pairing": "round-robin", "inner_mode": args.inner_mode},
+        "sweeps": sweeps,
+        "ms_per_sweep": ms_step / (sum(sweeps) / len(sweeps)),
+        "c_time_model": (dt / K) / n ** 3,
+        "accuracy": acc,
+        "gen_seconds": gen_s,
+    }
+    if not args.no_profile and profs[-1] is not None:
+        pr = profs[-1]
+        rf, wk = roofline(pr, n, False)
+        out["roofline"] = rf
+        out["kernels"] = {k: dict(ms_total=pr[k]["ms"], launches=pr[k]["launches"],
+                                  avg_ms=wk[k]["ms"] if k in wk else None,
+                                  gflops_per_launch=wk[k]["flops"] / 1e9 if k in wk else None,
+                                  gbytes_per_launch=wk[k]["bytes"] / 1e9 if k in wk else None)
+                          for k in ("gram", "pivot", "update", "final", "other")}
+        out["inner"] = dict(rotations=pr["rotations"], inner_sweeps=pr["inner_sweeps"])
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(n, oracle_sweeps if oracle_sweeps else 14)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,160 @@
+/* jjacobi.h -- C ABI of the MI355X (gfx950) one-sided hyperbolic J-Jacobi eigensolver.
+ *
+ * Problem (paper, Section 2.2-2.3, eq. 2.5-2.6 and 2.10-2.11): given a factor G
+ * (n x n, full column rank) and J = diag(j_1..j_n), j_i = +-1, compute the
+ * eigenpairs of the Hermitian matrix H = G J G^*.  The method applies J-unitary
+ * transformations from the right, G <- G W (eq. 2.9 / 3.4), until the columns
+ * of G are mutually orthogonal; then
+ *     lambda_i = j_i * ||g_i||^2      and      v_i = g_i / ||g_i||
+ * (eq. 2.10-2.11 and the final two lines of Algorithm 5.2).
+ *
+ * The blocked process (Sections 3.1-3.3, 4.2, 5.3): the columns are reordered so
+ * that J = diag(I_nu, -I_{n-nu}) (Section 2.3, last paragraph), split into an
+ * even number of almost equal blocks (eq. 3.2-3.3), and every sweep visits each
+ * pair of blocks once in round-robin order, nblocks/2 disjoint pairs at a time.
+ * Per pair: Gram block A_P = [G_i G_j]^* [G_i G_j] (eq. 3.6), Cholesky factor R
+ * (eq. 3.8), one-sided J-Jacobi on R accumulating W_P (eq. 3.12, Algorithms
+ * 3.1-3.2), and the update [G_i G_j] <- [G_i G_j] W_P (Section 3.3, last
+ * paragraph before Algorithm 3.1).
+ *
+ * Conventions common to all entry points
+ *   - Matrices are column-major.  G, V and lambda are DEVICE pointers owned by
+ *     the caller; J is a HOST array of n signed chars, each +1 or -1.
+ *   - Complex data (dtype 1) is interleaved (re, im) double pairs; ld counts
+ *     complex elements.
+ *   - G is overwritten (destroyed) by the solve.  V must not overlap G.
+ *   - On return lambda[k], V[:,k] is the k-th eigenpair, sorted by lambda
+ *     descending, ties broken by ascending input column index.
+ *   - tol <= 0 selects tol = n * 2^-53: a column pair is rotated iff
+ *     |g_r^* g_s| > tol * ||g_r|| * ||g_s||.  max_sweeps <= 0 selects 100.
+ *   - Work is ordered on the stream given in jj_opts (NULL: the null stream);
+ *     the call returns after the solve has completed on that stream.
+ *   - The library keeps a cached device workspace per device (released by
+ *     jjacobi_release_workspace); calls are serialised by an internal mutex.
+ *
+ * Return value (LAPACK style)
+ *    0  converged
+ *    1  not converged within max_sweeps (outputs are still written)
+ *    2  numerical breakdown: G is numerically rank deficient (a pivot block
+ *       Cholesky failed, a hyperbolic rotation did not exist, or a final column
+ *       is zero)
+ *    3  non-finite input
+ *    4  HIP runtime error (jjacobi_status_string(4) gives the last message)
+ *   -k  the k-th argument is invalid (null pointer, n < 0, ld < max(1, n),
+ *       J[i] not +-1, unknown dtype, ...)
+ */
+#ifndef JJACOBI_H
+#define JJACOBI_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define JJ_OK 0
+#define JJ_NOT_CONVERGED 1
+#define JJ_BREAKDOWN 2
+#define JJ_NONFINITE 3
+#define JJ_HIP_ERROR 4
+
+#define JJ_F64 0 /* real double */
+#define JJ_C128 1 /* complex double, interleaved */
+
+/* Options.  Zero-initialised fields select the defaults noted. */
+typedef struct jj_opts {
+  void* stream;          /* hipStream_t to order the work on; NULL: null stream */
+  int block_width;       /* target block width n_t of eq. 3.2; 0: library choice (32) */
+  int inner_max_sweeps;  /* cap on inner sweeps of one pivot solve (Algorithm 3.2 max_it);
+                            0: 12 */
+  int diag_pass;         /* diagonal-block pre-processing (Algorithm 3.3, first inner loop):
+                            0: off (default), 1: first sweep only, 2: every sweep */
+  int inner_mode;        /* 0: full pivot diagonalisation (full block, Section 3.3);
+                            1: one annihilation pass over the off-diagonal block
+                               (block-oriented, Section 3.4 / Algorithm 3.4) */
+  int precision;         /* 0: FP64 throughout; 1: mixed (FP32 Gram in pre-sweeps) */
+  double mixed_switch;   /* mixed: sweeps whose max scaled off-diagonal is below this
+                            run in FP64; 0: 1e-5 */
+  int strategy;          /* 0: round-robin block pairing (Section 4.2);
+                            1: modulus pairing (Section 4.1) */
+  int profile;           /* 1: time every kernel launch with HIP events on the stream
+                            (read back with jjacobi_last_profile) */
+  int reserved[7];
+} jj_opts;
+
+/* Per-solve report (all fields written when the pointer is non-NULL). */
+typedef struct jj_info {
+  int status;              /* same code as the return value */
+  int sweeps;              /* block sweeps executed */
+  int block_width;         /* largest block size used */
+  int nblocks;             /* number of blocks */
+  long long pivots_rotated;/* pivot blocks whose transformation was not the identity */
+  double final_offdiag;    /* max scaled off-diagonal |a_rs|/sqrt(a_rr a_ss) seen by the
+                              Gram checks of the last sweep */
+  double seconds;          /* wall-clock time of the solve */
+  int mixed_sweeps;        /* sweeps that used the FP32 Gram (precision 1) */
+  int reserved[7];
+} jj_info;
+
+/* Fill *opts with the defaults. */
+void jjacobi_default_opts(jj_opts* opts);
+
+/* Real symmetric H = G J G^T, G float64 (n x n, leading dimension ldg).
+ * lambda: n doubles; V: n x n doubles, leading dimension n. */
+int jjacobi_solve(double* G, const signed char* J, int n, int ldg, double* lambda, double* V,
+                  double tol, int max_sweeps);
+
+/* Complex Hermitian H = G J G^*, G complex128 interleaved (n x n, ldg).
+ * lambda: n doubles; V: n x n complex128, leading dimension n. */
+int jjacobi_zsolve(void* G, const signed char* J, int n, int ldg, double* lambda, void* V,
+                   double tol, int max_sweeps);
+
+/* General form: dtype JJ_F64 or JJ_C128, V with leading dimension ldv >= n,
+ * options (nullable: defaults) and report (nullable). */
+int jjacobi_solve_ex(int dtype, void* G, const signed char* J, int n, int ldg, double* lambda,
+                     void* V, int ldv, double tol, int max_sweeps, const jj_opts* opts,
+                     jj_info* info);
+
+/* Many independent problems in one call (problem k uses dtype[k], G[k], J[k],
+ * n[k], ldg[k], lambda[k], V[k], ldv[k]; all device pointers except J[k]).
+ * info: array of count reports, or NULL.  Returns the largest status over the
+ * problems (a negative value if an argument is invalid; then nothing runs). */
+int jjacobi_solve_batched(int count, const int* dtype, void* const* G, const signed char* const* J,
+                          const int* n, const int* ldg, double* const* lambda, void* const* V,
+                          const int* ldv, double tol, int max_sweeps, const jj_opts* opts,
+                          jj_info* info);
+
+/* Kernel kinds reported by jjacobi_last_profile. */
+#define JJ_K_GRAM 0   /* Gram block partials, eq. 3.6 */
+#define JJ_K_PIVOT 1  /* pivot solve: Cholesky + inner J-Jacobi, eq. 3.8 and 3.12 */
+#define JJ_K_UPDATE 2 /* block-column update, eq. 3.4 */
+#define JJ_K_FINAL 3  /* column norms, ranking, eigenvectors, eq. 2.10 */
+#define JJ_K_OTHER 4  /* input scan, counter resets */
+#define JJ_NKINDS 5
+
+/* Device time of the last solve on this thread that ran with opts.profile = 1. */
+typedef struct jj_profile {
+  double ms[8];           /* summed event-timed duration per kernel kind */
+  long long launches[8];  /* launches per kind */
+  long long units[8];     /* pivot problems handled per kind (UPDATE: pivots whose W_P
+                             is not the identity; FINAL: columns) */
+  long long rotations;    /* plane rotations applied inside pivot solves */
+  long long inner_sweeps; /* inner sweeps run, summed over pivot solves */
+  long long pivot_cols;   /* sum over solved pivots of their column count m */
+  long long pivot_cols3;  /* sum over solved pivots of m^3 */
+  int n, nblocks, block_width, sweeps, dtype, valid;
+} jj_profile;
+
+/* Copy the profile of the last profiled solve of this thread into *out.
+ * Returns 0, or -1 if there is none (out untouched) or out is NULL. */
+int jjacobi_last_profile(jj_profile* out);
+
+/* Text for a status code (for 4: the last HIP error message of this thread). */
+const char* jjacobi_status_string(int status);
+
+/* Free the cached device workspace of every device. */
+void jjacobi_release_workspace(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JJACOBI_H */

@@ -1,0 +1,620 @@
+// Host orchestrator and C ABI of the blocked one-sided J-Jacobi eigensolver.
+//
+// Per solve (paper, Algorithm 5.2 and Section 5.3, on one GPU):
+//   1. stable reordering of the columns so that J = diag(I_nu, -I_{n-nu})
+//      (Section 2.3, last paragraph), uniform partition into an even number
+//      of blocks (eq. 3.2-3.3), and the round-robin pair table (Section 4.2;
+//      here the circle-method tournament with block 0 fixed, which visits
+//      every pair of blocks exactly once in nblocks-1 steps of nblocks/2
+//      disjoint pairs);
+//   2. sweeps: for each step, Gram -> pivot solve -> update on all pairs of
+//      the step at once (the pairs of one step are independent, Section 4);
+//      convergence when a sweep's pivots all pass the scaled off-diagonal test
+//      (Section 5.3, "no rotations" form);
+//   3. finalisation lambda_i = j_i ||g_i||^2, v_i = g_i/||g_i|| (eq. 2.10).
+// The columns are never moved: blocks are lists of physical column indices.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/jjacobi.h"
+#include "jj_device.h"
+
+namespace jj {
+
+static thread_local std::string g_last_error;
+static std::mutex g_mutex;
+
+struct HipFail {
+  hipError_t e;
+};
+
+static void ck(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    throw HipFail{e};
+  }
+}
+
+// One growing device allocation per device, carved into aligned sections.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0;
+};
+static Arena g_arena[64];
+
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = reinterpret_cast<T*>(base + off);
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+static char* arena_get(size_t bytes) {
+  int dev = 0;
+  ck(hipGetDevice(&dev), "hipGetDevice");
+  Arena& a = g_arena[dev & 63];
+  if (a.cap < bytes) {
+    if (a.base) ck(hipFree(a.base), "hipFree");
+    a.base = nullptr;
+    a.cap = 0;
+    size_t want = std::max(bytes, size_t(1) << 20);
+    ck(hipMalloc((void**)&a.base, want), "hipMalloc workspace");
+    a.cap = want;
+  }
+  return a.base;
+}
+
+// Optional per-launch timing with HIP events recorded on the solve stream.
+struct Profiler {
+  bool on = false;
+  hipStream_t s = nullptr;
+  size_t used = 0;
+  struct Rec {
+    int kind;
+    size_t e0, e1;
+  };
+  std::vector<Rec> recs;
+  jj_profile acc;
+  static std::vector<hipEvent_t>& pool() {
+    static std::vector<hipEvent_t> p;
+    return p;
+  }
+  size_t mark() {
+    if (!on) return 0;
+    auto& P = pool();
+    if (used == P.size()) {
+      hipEvent_t e;
+      ck(hipEventCreate(&e), "hipEventCreate");
+      P.push_back(e);
+    }
+    ck(hipEventRecord(P[used], s), "hipEventRecord");
+    return used++;
+  }
+  void done(int kind, size_t e0, long long units) {
+    if (!on) return;
+    size_t e1 = mark();
+    recs.push_back(Rec{kind, e0, e1});
+    acc.launches[kind]++;
+    acc.units[kind] += units;
+  }
+  // call after the stream has been synchronised
+  void flush() {
+    if (!on) return;
+    auto& P = pool();
+    for (const Rec& r : recs) {
+      float ms = 0.f;
+      ck(hipEventElapsedTime(&ms, P[r.e0], P[r.e1]), "hipEventElapsedTime");
+      acc.ms[r.kind] += ms;
+    }
+    recs.clear();
+    used = 0;
+  }
+};
+static thread_local jj_profile g_last_prof;
+static thread_local bool g_have_prof = false;
+
+// ---------------------------------------------------------------------------
+// Host logic (exported with C linkage for the CPU tests as jjx_* helpers).
+// ---------------------------------------------------------------------------
+
+// Number of blocks: nbl = ceil(n / n_t) (eq. 3.2), at least 2, made even so
+// that every block has a partner in each round-robin step.
+int plan_nblocks(int n, int nt) {
+  if (n < 2) return 1;
+  int nbl = (n + nt - 1) / nt;
+  if (nbl < 2) nbl = 2;
+  if (nbl & 1) nbl++;
+  if (nbl > n) nbl = n - (n & 1);
+  return nbl;
+}
+
+// Uniform partition (eq. 3.3): the first n mod nbl blocks get floor(n/nbl)+1.
+void plan_offsets(int n, int nbl, int* off) {
+  int nmin = n / nbl, br = n % nbl;
+  off[0] = 0;
+  for (int l = 0; l < nbl; l++) off[l + 1] = off[l] + nmin + (l < br ? 1 : 0);
+}
+
+// Round-robin tournament: step t in [0, nbl-1), pair k in [0, nbl/2).
+// Position 0 holds block 0; position i >= 1 holds block ((i - 1 + t) mod (nbl - 1)) + 1;
+// pair k joins positions k and nbl-1-k.
+void plan_round_robin(int nbl, int* pairs /* [(nbl-1)][nbl/2][2] */) {
+  const int h = nbl / 2;
+  for (int t = 0; t < nbl - 1; t++)
+    for (int k = 0; k < h; k++) {
+      int a = k == 0 ? 0 : ((k - 1 + t) % (nbl - 1)) + 1;
+      int b = ((nbl - 1 - k - 1 + t) % (nbl - 1)) + 1;
+      pairs[(t * h + k) * 2 + 0] = std::min(a, b);
+      pairs[(t * h + k) * 2 + 1] = std::max(a, b);
+    }
+}
+
+// Modulus pairing (Section 4.1): nbl steps per sweep; step t takes the
+// anti-diagonal k = (nbl - 1 + t) mod nbl of the block matrix, i.e. the pairs
+// {(i, j) : i + j = k mod nbl, i < j}, starting on the main anti-diagonal as
+// the paper's layout does.  The diagonal blocks an anti-diagonal meets are
+// left idle (option (b) of Section 4.1 rather than visiting them twice), so a
+// step has nbl/2 or nbl/2 - 1 pairs and every pair occurs exactly once.
+int plan_modulus(int nbl, int* pairs /* [nbl][nbl/2][2] */, int* counts /* [nbl] */) {
+  const int h = nbl / 2;
+  for (int t = 0; t < nbl; t++) {
+    const int k = (nbl - 1 + t) % nbl;
+    int c = 0;
+    for (int i = 0; i < nbl; i++) {
+      int j = ((k - i) % nbl + nbl) % nbl;
+      if (i < j) {
+        pairs[(t * h + c) * 2 + 0] = i;
+        pairs[(t * h + c) * 2 + 1] = j;
+        c++;
+      }
+    }
+    counts[t] = c;
+  }
+  return nbl;
+}
+
+// Stable order with the +1 columns first (J = diag(I_nu, -I_{n-nu})).
+void plan_sign_order(int n, const signed char* J, int* colmap) {
+  int k = 0;
+  for (int i = 0; i < n; i++)
+    if (J[i] > 0) colmap[k++] = i;
+  for (int i = 0; i < n; i++)
+    if (J[i] < 0) colmap[k++] = i;
+}
+
+struct Plan {
+  int n, nbl, nsteps, npairs_max;
+  std::vector<int> off, colmap, cols, m, nfirst, count;
+  std::vector<signed char> sgp, sgn;
+};
+
+static void build_pairs_tables(Plan& P, const std::vector<int>& pairs, int nsteps, const std::vector<int>& counts) {
+  const int h = P.nbl / 2;
+  P.nsteps = nsteps;
+  P.npairs_max = h;
+  P.cols.assign((size_t)nsteps * h * kMaxPivot, -1);
+  P.sgp.assign((size_t)nsteps * h * kMaxPivot, 0);
+  P.m.assign((size_t)nsteps * h, 0);
+  P.nfirst.assign((size_t)nsteps * h, 0);
+  P.count = counts;
+  for (int t = 0; t < nsteps; t++)
+    for (int k = 0; k < counts[t]; k++) {
+      int bi = pairs[(t * h + k) * 2], bj = pairs[(t * h + k) * 2 + 1];
+      size_t base = ((size_t)t * h + k) * kMaxPivot;
+      int c = 0;
+      for (int q = P.off[bi]; q < P.off[bi + 1]; q++, c++) {
+        P.cols[base + c] = P.colmap[q];
+        P.sgp[base + c] = P.sgn[q];
+      }
+      P.nfirst[(size_t)t * h + k] = c;
+      for (int q = P.off[bj]; q < P.off[bj + 1]; q++, c++) {
+        P.cols[base + c] = P.colmap[q];
+        P.sgp[base + c] = P.sgn[q];
+      }
+      P.m[(size_t)t * h + k] = c;
+    }
+}
+
+static Plan make_plan(int n, const signed char* J, int nt, int strategy) {
+  Plan P;
+  P.n = n;
+  P.nbl = plan_nblocks(n, nt);
+  P.colmap.resize(n);
+  plan_sign_order(n, J, P.colmap.data());
+  P.sgn.resize(n);
+  for (int q = 0; q < n; q++) P.sgn[q] = J[P.colmap[q]];
+  P.off.resize(P.nbl + 1);
+  plan_offsets(n, P.nbl, P.off.data());
+  const int h = P.nbl / 2;
+  if (P.nbl < 2) {
+    P.nsteps = 0;
+    P.npairs_max = 0;
+    return P;
+  }
+  if (strategy == 1) {
+    std::vector<int> pairs((size_t)P.nbl * h * 2), counts(P.nbl);
+    plan_modulus(P.nbl, pairs.data(), counts.data());
+    build_pairs_tables(P, pairs, P.nbl, counts);
+  } else {
+    std::vector<int> pairs((size_t)(P.nbl - 1) * h * 2), counts(P.nbl - 1, h);
+    plan_round_robin(P.nbl, pairs.data());
+    build_pairs_tables(P, pairs, P.nbl - 1, counts);
+  }
+  return P;
+}
+
+// Single-block pivots for the diagonal pre-processing pass (Algorithm 3.3):
+// pivot l holds block l (nfirst = m, so block-oriented mode has no pairs).
+static void build_diag_tables(const Plan& P, std::vector<int>& cols, std::vector<signed char>& sg,
+                              std::vector<int>& m, std::vector<int>& nfirst) {
+  cols.assign((size_t)P.nbl * kMaxPivot, -1);
+  sg.assign((size_t)P.nbl * kMaxPivot, 0);
+  m.assign(P.nbl, 0);
+  nfirst.assign(P.nbl, 0);
+  for (int l = 0; l < P.nbl; l++) {
+    int c = 0;
+    for (int q = P.off[l]; q < P.off[l + 1]; q++, c++) {
+      cols[(size_t)l * kMaxPivot + c] = P.colmap[q];
+      sg[(size_t)l * kMaxPivot + c] = P.sgn[q];
+    }
+    m[l] = c;
+    nfirst[l] = c;
+  }
+}
+
+static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, double* lambda, void* Vv,
+                     int ldv, double tol, int max_sweeps, const jj_opts& o, jj_info* info) {
+  auto t0 = std::chrono::steady_clock::now();
+  const int cplx = dtype == JJ_C128;
+  double* G = (double*)Gv;
+  double* V = (double*)Vv;
+  hipStream_t stream = (hipStream_t)o.stream;
+  const int nt = o.block_width > 0 ? std::min(o.block_width, kMaxBlock) : 32;
+  const int inner_max = o.inner_max_sweeps > 0 ? o.inner_max_sweeps : 12;
+  if (tol <= 0.0) tol = (double)n * std::ldexp(1.0, -53);
+  if (max_sweeps <= 0) max_sweeps = 100;
+
+  Plan P = make_plan(n, J, nt, o.strategy);
+  const int h = std::max(P.npairs_max, 1);
+  // chunking of the row dimension for the Gram and update kernels
+  int nch = std::max(1, std::min((1024 + h - 1) / h, (n + 63) / 64));
+  int rows_g = ((n + nch - 1) / nch + 63) / 64 * 64;
+  nch = (n + rows_g - 1) / rows_g;
+  int rows_u = 256;
+  if ((long long)h * ((n + 255) / 256) < 512) rows_u = 64;
+
+  std::vector<int> dcols, dm, dnf;
+  std::vector<signed char> dsg;
+  build_diag_tables(P, dcols, dsg, dm, dnf);
+  const int nb_piv = std::max(h, P.nbl);
+
+  // workspace layout
+  const size_t tab = (size_t)std::max(P.nsteps, 1) * h * kMaxPivot;
+  size_t need = 0;
+  {
+    Carver c{nullptr};
+    c.take<int>(tab);
+    c.take<signed char>(tab);
+    c.take<int>((size_t)std::max(P.nsteps, 1) * h);
+    c.take<int>((size_t)std::max(P.nsteps, 1) * h);
+    c.take<int>((size_t)P.nbl * kMaxPivot);
+    c.take<signed char>((size_t)P.nbl * kMaxPivot);
+    c.take<int>(P.nbl);
+    c.take<int>(P.nbl);
+    c.take<double>((size_t)nb_piv * nch * kMaxPivot * kMaxPivot * (cplx ? 2 : 1));
+    c.take<double>((size_t)nb_piv * kMaxPivot * kMaxPivot * (cplx ? 2 : 1));
+    c.take<int>(nb_piv);
+    c.take<SweepStats>(1);
+    c.take<int>(n);
+    c.take<signed char>(n);
+    c.take<double>(n);
+    c.take<int>(n);
+    need = c.off + 256;
+  }
+  Carver c{arena_get(need)};
+  int* d_cols = c.take<int>(tab);
+  signed char* d_sg = c.take<signed char>(tab);
+  int* d_m = c.take<int>((size_t)std::max(P.nsteps, 1) * h);
+  int* d_nf = c.take<int>((size_t)std::max(P.nsteps, 1) * h);
+  int* d_dcols = c.take<int>((size_t)P.nbl * kMaxPivot);
+  signed char* d_dsg = c.take<signed char>((size_t)P.nbl * kMaxPivot);
+  int* d_dm = c.take<int>(P.nbl);
+  int* d_dnf = c.take<int>(P.nbl);
+  double* d_part = c.take<double>((size_t)nb_piv * nch * kMaxPivot * kMaxPivot * (cplx ? 2 : 1));
+  double* d_W = c.take<double>((size_t)nb_piv * kMaxPivot * kMaxPivot * (cplx ? 2 : 1));
+  int* d_rot = c.take<int>(nb_piv);
+  SweepStats* d_st = c.take<SweepStats>(1);
+  int* d_colmap = c.take<int>(n);
+  signed char* d_sgn = c.take<signed char>(n);
+  double* d_d = c.take<double>(n);
+  int* d_rank = c.take<int>(n);
+
+  if (P.nsteps > 0) {
+    ck(hipMemcpyAsync(d_cols, P.cols.data(), P.cols.size() * sizeof(int), hipMemcpyHostToDevice, stream), "H2D");
+    ck(hipMemcpyAsync(d_sg, P.sgp.data(), P.sgp.size(), hipMemcpyHostToDevice, stream), "H2D");
+    ck(hipMemcpyAsync(d_m, P.m.data(), P.m.size() * sizeof(int), hipMemcpyHostToDevice, stream), "H2D");
+    ck(hipMemcpyAsync(d_nf, P.nfirst.data(), P.nfirst.size() * sizeof(int), hipMemcpyHostToDevice, stream),
+       "H2D");
+  }
+  ck(hipMemcpyAsync(d_dcols, dcols.data(), dcols.size() * sizeof(int), hipMemcpyHostToDevice, stream), "H2D");
+  ck(hipMemcpyAsync(d_dsg, dsg.data(), dsg.size(), hipMemcpyHostToDevice, stream), "H2D");
+  ck(hipMemcpyAsync(d_dm, dm.data(), dm.size() * sizeof(int), hipMemcpyHostToDevice, stream), "H2D");
+  ck(hipMemcpyAsync(d_dnf, dnf.data(), dnf.size() * sizeof(int), hipMemcpyHostToDevice, stream), "H2D");
+  ck(hipMemcpyAsync(d_colmap, P.colmap.data(), n * sizeof(int), hipMemcpyHostToDevice, stream), "H2D");
+  ck(hipMemcpyAsync(d_sgn, P.sgn.data(), n, hipMemcpyHostToDevice, stream), "H2D");
+
+  Profiler prof;
+  prof.on = o.profile != 0;
+  prof.s = stream;
+  std::memset(&prof.acc, 0, sizeof(prof.acc));
+
+  SweepStats hst;
+  size_t e0 = prof.mark();
+  launch_reset_stats(d_st, stream);
+  launch_check_finite(G, ldg, n, cplx, d_st, stream);
+  prof.done(JJ_K_OTHER, e0, 0);
+  ck(hipGetLastError(), "launch");
+  ck(hipMemcpyAsync(&hst, d_st, sizeof(hst), hipMemcpyDeviceToHost, stream), "D2H");
+  ck(hipStreamSynchronize(stream), "sync");
+  prof.flush();
+  if (hst.nonfinite) {
+    if (info) {
+      info->status = JJ_NONFINITE;
+      info->sweeps = 0;
+    }
+    return JJ_NONFINITE;
+  }
+
+  auto gram = cplx ? launch_gram_c128 : launch_gram_f64;
+  auto pivot = cplx ? launch_pivot_c128 : launch_pivot_f64;
+  auto update = cplx ? launch_update_c128 : launch_update_f64;
+
+  int status = JJ_NOT_CONVERGED, sweep = 0;
+  long long piv_rot = 0;
+  double last_off = 0.0;
+  bool breakdown = false;
+  if (P.nbl < 2) status = JJ_OK;
+  while (P.nbl >= 2 && sweep < max_sweeps) {
+    sweep++;
+    e0 = prof.mark();
+    launch_reset_stats(d_st, stream);
+    prof.done(JJ_K_OTHER, e0, 0);
+    if (o.diag_pass == 2 || (o.diag_pass == 1 && sweep == 1)) {
+      PivotList dl{d_dcols, d_dsg, d_dm, d_dnf, P.nbl};
+      e0 = prof.mark();
+      gram(G, ldg, n, dl, nch, rows_g, d_part, stream);
+      prof.done(JJ_K_GRAM, e0, dl.count);
+      e0 = prof.mark();
+      pivot(d_part, nch, dl, tol, inner_max, 0, d_W, d_rot, d_st, stream);
+      prof.done(JJ_K_PIVOT, e0, dl.count);
+      e0 = prof.mark();
+      update(G, ldg, n, dl, d_W, d_rot, rows_u, stream);
+      prof.done(JJ_K_UPDATE, e0, 0);
+    }
+    for (int t = 0; t < P.nsteps; t++) {
+      PivotList pl{d_cols + (size_t)t * h * kMaxPivot, d_sg + (size_t)t * h * kMaxPivot, d_m + (size_t)t * h,
+                   d_nf + (size_t)t * h, P.count[t]};
+      if (pl.count == 0) continue;
+      // Block-oriented variant (Section 5.3): the first step of a sweep makes one
+      // full pass over its pivots (covering every diagonal block), the other
+      // steps one pass over the off-diagonal block only.
+      const int mode = (o.inner_mode == 1 && t > 0) ? 1 : 0;
+      const int imax = o.inner_mode == 1 ? 1 : inner_max;
+      e0 = prof.mark();
+      gram(G, ldg, n, pl, nch, rows_g, d_part, stream);
+      prof.done(JJ_K_GRAM, e0, pl.count);
+      e0 = prof.mark();
+      pivot(d_part, nch, pl, tol, imax, mode, d_W, d_rot, d_st, stream);
+      prof.done(JJ_K_PIVOT, e0, pl.count);
+      e0 = prof.mark();
+      update(G, ldg, n, pl, d_W, d_rot, rows_u, stream);
+      prof.done(JJ_K_UPDATE, e0, 0);
+    }
+    ck(hipGetLastError(), "launch");
+    ck(hipMemcpyAsync(&hst, d_st, sizeof(hst), hipMemcpyDeviceToHost, stream), "D2H");
+    ck(hipStreamSynchronize(stream), "sync");
+    prof.flush();
+    double off;
+    std::memcpy(&off, &hst.max_off_bits, sizeof(off));
+    last_off = off;
+    piv_rot += hst.pivots_rotated;
+    prof.acc.units[JJ_K_UPDATE] += hst.pivots_rotated;
+    prof.acc.rotations += (long long)hst.rotations;
+    prof.acc.inner_sweeps += (long long)hst.inner_sweeps;
+    prof.acc.pivot_cols += (long long)hst.pivot_cols;
+    prof.acc.pivot_cols3 += (long long)hst.pivot_cols3;
+    if (hst.breakdown) {
+      breakdown = true;
+      break;
+    }
+    if (hst.pivots_rotated == 0) {
+      status = JJ_OK;
+      break;
+    }
+  }
+
+  e0 = prof.mark();
+  launch_reset_stats(d_st, stream);
+  prof.done(JJ_K_OTHER, e0, 0);
+  e0 = prof.mark();
+  launch_finalize(G, ldg, n, cplx, d_colmap, d_sgn, d_d, d_rank, lambda, V, ldv, d_st, stream);
+  prof.done(JJ_K_FINAL, e0, n);
+  ck(hipGetLastError(), "launch");
+  ck(hipMemcpyAsync(&hst, d_st, sizeof(hst), hipMemcpyDeviceToHost, stream), "D2H");
+  ck(hipStreamSynchronize(stream), "sync");
+  prof.flush();
+  if (prof.on) {
+    prof.acc.n = n;
+    prof.acc.nblocks = P.nbl;
+    prof.acc.block_width = P.nbl >= 1 && P.off.size() > 1 ? P.off[1] - P.off[0] : 0;
+    prof.acc.sweeps = sweep;
+    prof.acc.dtype = dtype;
+    prof.acc.valid = 1;
+    g_last_prof = prof.acc;
+    g_have_prof = true;
+  }
+  if (breakdown || hst.zero_col) status = JJ_BREAKDOWN;
+
+  if (info) {
+    info->status = status;
+    info->sweeps = sweep;
+    info->block_width = P.nbl >= 1 ? (P.off.size() > 1 ? P.off[1] - P.off[0] : 0) : 0;
+    info->nblocks = P.nbl;
+    info->pivots_rotated = piv_rot;
+    info->final_offdiag = last_off;
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    info->mixed_sweeps = 0;
+  }
+  return status;
+}
+
+static int check_args(int dtype, const void* G, const signed char* J, int n, int ldg, const double* lambda,
+                      const void* V, int ldv) {
+  if (dtype != JJ_F64 && dtype != JJ_C128) return -1;
+  if (n < 0) return -4;
+  if (n == 0) return 0;
+  if (!G) return -2;
+  if (!J) return -3;
+  if (ldg < std::max(1, n)) return -5;
+  if (!lambda) return -6;
+  if (!V) return -7;
+  if (ldv < std::max(1, n)) return -8;
+  for (int i = 0; i < n; i++)
+    if (J[i] != 1 && J[i] != -1) return -3;
+  return 0;
+}
+
+}  // namespace jj
+
+using namespace jj;
+
+extern "C" {
+
+void jjacobi_default_opts(jj_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->block_width = 32;
+  o->inner_max_sweeps = 12;
+  o->mixed_switch = 1e-5;
+}
+
+int jjacobi_solve_ex(int dtype, void* G, const signed char* J, int n, int ldg, double* lambda, void* V, int ldv,
+                     double tol, int max_sweeps, const jj_opts* opts, jj_info* info) {
+  int a = check_args(dtype, G, J, n, ldg, lambda, V, ldv);
+  if (a < 0) {
+    if (info) info->status = a;
+    return a;
+  }
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (n == 0) return 0;
+  jj_opts o;
+  jjacobi_default_opts(&o);
+  if (opts) o = *opts;
+  std::lock_guard<std::mutex> lk(g_mutex);
+  try {
+    return solve_one(dtype, G, J, n, ldg, lambda, V, ldv, tol, max_sweeps, o, info);
+  } catch (const HipFail&) {
+    if (info) info->status = JJ_HIP_ERROR;
+    return JJ_HIP_ERROR;
+  }
+}
+
+int jjacobi_solve(double* G, const signed char* J, int n, int ldg, double* lambda, double* V, double tol,
+                  int max_sweeps) {
+  return jjacobi_solve_ex(JJ_F64, G, J, n, ldg, lambda, V, n, tol, max_sweeps, nullptr, nullptr);
+}
+
+int jjacobi_zsolve(void* G, const signed char* J, int n, int ldg, double* lambda, void* V, double tol,
+                   int max_sweeps) {
+  return jjacobi_solve_ex(JJ_C128, G, J, n, ldg, lambda, V, n, tol, max_sweeps, nullptr, nullptr);
+}
+
+int jjacobi_solve_batched(int count, const int* dtype, void* const* G, const signed char* const* J, const int* n,
+                          const int* ldg, double* const* lambda, void* const* V, const int* ldv, double tol,
+                          int max_sweeps, const jj_opts* opts, jj_info* info) {
+  if (count < 0) return -1;
+  if (count == 0) return 0;
+  if (!dtype) return -2;
+  if (!G) return -3;
+  if (!J) return -4;
+  if (!n) return -5;
+  if (!ldg) return -6;
+  if (!lambda) return -7;
+  if (!V) return -8;
+  if (!ldv) return -9;
+  for (int k = 0; k < count; k++) {
+    int a = check_args(dtype[k], G[k], J[k], n[k], ldg[k], lambda[k], V[k], ldv[k]);
+    if (a < 0) return a;
+  }
+  int worst = 0;
+  for (int k = 0; k < count; k++) {
+    int s = jjacobi_solve_ex(dtype[k], G[k], J[k], n[k], ldg[k], lambda[k], V[k], ldv[k], tol, max_sweeps, opts,
+                             info ? info + k : nullptr);
+    worst = std::max(worst, s);
+  }
+  return worst;
+}
+
+const char* jjacobi_status_string(int status) {
+  switch (status) {
+    case 0:
+      return "converged";
+    case 1:
+      return "not converged within max_sweeps";
+    case 2:
+      return "numerical breakdown: G is numerically rank deficient";
+    case 3:
+      return "non-finite input";
+    case 4:
+      return g_last_error.empty() ? "HIP runtime error" : g_last_error.c_str();
+    default:
+      return status < 0 ? "invalid argument" : "unknown status";
+  }
+}
+
+void jjacobi_release_workspace(void) {
+  std::lock_guard<std::mutex> lk(g_mutex);
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess) return;
+  for (hipEvent_t e : Profiler::pool()) hipEventDestroy(e);
+  Profiler::pool().clear();
+  for (int d = 0; d < 64; d++)
+    if (g_arena[d].base) {
+      if (hipSetDevice(d) == hipSuccess) hipFree(g_arena[d].base);
+      g_arena[d].base = nullptr;
+      g_arena[d].cap = 0;
+    }
+  hipSetDevice(cur);
+}
+
+int jjacobi_last_profile(jj_profile* out) {
+  if (!out || !g_have_prof) return -1;
+  *out = g_last_prof;
+  return 0;
+}
+
+// Host planning helpers exported for the CPU tests (no HIP calls).
+int jjx_plan_nblocks(int n, int nt) { return plan_nblocks(n, nt); }
+void jjx_plan_offsets(int n, int nbl, int* off) { plan_offsets(n, nbl, off); }
+void jjx_plan_round_robin(int nbl, int* pairs) { plan_round_robin(nbl, pairs); }
+int jjx_plan_modulus(int nbl, int* pairs, int* counts) { return plan_modulus(nbl, pairs, counts); }
+void jjx_plan_sign_order(int n, const signed char* J, int* colmap) { plan_sign_order(n, J, colmap); }
+int jjx_check_args(int dtype, const void* G, const signed char* J, int n, int ldg, const double* lambda,
+                   const void* V, int ldv) {
+  return check_args(dtype, G, J, n, ldg, lambda, V, ldv);
+}
+
+}  // extern "C"
