@@ -67,9 +67,12 @@ typedef struct jj_opts {
                             0: 12 */
   int diag_pass;         /* diagonal-block pre-processing (Algorithm 3.3, first inner loop):
                             0: off (default), 1: first sweep only, 2: every sweep */
-  int inner_mode;        /* 0: full pivot diagonalisation (full block, Section 3.3);
-                            1: one annihilation pass over the off-diagonal block
-                               (block-oriented, Section 3.4 / Algorithm 3.4) */
+  int inner_mode;        /* 0 (default): block-oriented (Section 3.4, Algorithm 5.1): the
+                               first step of a sweep makes one full inner pass per
+                               pivot, the other steps one pass over the off-diagonal
+                               block;
+                            1: full pivot diagonalisation (full block, Section 3.3),
+                               up to inner_max_sweeps inner sweeps */
   int precision;         /* 0: FP64 throughout; 1: mixed (FP32 Gram in pre-sweeps) */
   double mixed_switch;   /* mixed: sweeps whose max scaled off-diagonal is below this
                             run in FP64; 0: 1e-5 */

@@ -105,252 +105,12 @@ __global__ __launch_bounds__(256) void k_gram_f64(const double* __restrict__ G, 
 }
 
 // ---------------------------------------------------------------------------
-// Rotation parameters (paper, Algorithm 3.1 with sigma = +j_r j_s; real case
-// eta = a_rs).  Returns 0: no rotation needed, 1: rotation (cs, sn) computed,
-// -1: hyperbolic rotation does not exist (|theta| <= 1).
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int rot_params(double arr, double ass, double ars, double sigma, double tol,
-                                          double* cs, double* sn) {
-  if (!(fabs(ars) > tol * sqrt(arr) * sqrt(ass))) return 0;
-  double theta = sigma * (ass - sigma * arr) / (2.0 * ars);
-  double at = fabs(theta);
-  if (sigma < 0.0 && at <= 1.0) return -1;
-  double sg = theta < 0.0 ? -1.0 : 1.0;
-  double t;
-  if (at > 1.0)
-    t = sg / (at * (1.0 + sqrt(1.0 + sigma / (theta * theta))));
-  else
-    t = sg / (at + sqrt(theta * theta + sigma));
-  double c;
-  if (sigma > 0.0)
-    c = 1.0 / sqrt(1.0 + t * t);
-  else
-    c = 1.0 / sqrt((1.0 - fabs(t)) * (1.0 + fabs(t)));
-  *cs = c;
-  *sn = c * t;
-  return 1;
-}
-
-// ---------------------------------------------------------------------------
-// Pivot solve.  Grid P, 256 threads.  LDS holds R and W_P column-major with
-// leading dimension 65.  Inner ordering: circle round-robin on the m' = m
-// rounded up to even columns (column 0 fixed, the rest rotate), m'/2 disjoint
-// column pairs per round handled by groups of 8 lanes.
-// inner_mode 0: full diagonalisation (repeat inner sweeps until one applies no
-// rotation, at most inner_max).  inner_mode 1: a single pass over the pairs
-// (r in the first block, s in the second) of the off-diagonal block.
-// ---------------------------------------------------------------------------
-constexpr int LDR = kMaxPivot + 1;
-
-__global__ __launch_bounds__(256) void k_pivot_f64(const double* __restrict__ part, int nch,
-                                                   const int* __restrict__ mlist, const int* __restrict__ nfirst,
-                                                   const signed char* __restrict__ sgl, double tol, int inner_max,
-                                                   int inner_mode, double* __restrict__ Wout,
-                                                   int* __restrict__ rotflag, SweepStats* st) {
-  __shared__ double R[kMaxPivot * LDR];
-  __shared__ double W[kMaxPivot * LDR];
-  __shared__ double redv[256];
-  __shared__ int s_cnt, s_bad, s_total, s_sweeps;
-  __shared__ double s_piv;
-  const int p = blockIdx.x, tid = threadIdx.x;
-  const int m = mlist[p];
-  const signed char* sg = sgl + p * kMaxPivot;
-
-  // 1. A_P = sum of the chunk partials (upper tiles), mirrored
-  const double* P = part + (size_t)p * nch * (kMaxPivot * kMaxPivot);
-  for (int e = tid; e < kMaxPivot * kMaxPivot; e += 256) {
-    int r = e >> 6, c = e & 63;
-    if (r < m && c < m && (r >> 4) <= (c >> 4)) {
-      double s = 0.0;
-      for (int k = 0; k < nch; k++) s += P[(size_t)k * (kMaxPivot * kMaxPivot) + e];
-      R[c * LDR + r] = s;
-    }
-  }
-  if (tid == 0) {
-    s_bad = 0;
-    s_total = 0;
-    s_sweeps = 0;
-  }
-  __syncthreads();
-  for (int e = tid; e < kMaxPivot * kMaxPivot; e += 256) {
-    int r = e >> 6, c = e & 63;
-    if (r < m && c < m && r > c) R[c * LDR + r] = R[r * LDR + c];
-  }
-  __syncthreads();
-
-  // 2. convergence test on the scaled off-diagonal, and zero / non-finite diagonal
-  double off = 0.0;
-  for (int e = tid; e < kMaxPivot * kMaxPivot; e += 256) {
-    int r = e >> 6, c = e & 63;
-    if (r < m && c < m && r < c) {
-      double v = fabs(R[c * LDR + r]) / (sqrt(R[r * LDR + r]) * sqrt(R[c * LDR + c]));
-      off = fmax(off, v);
-    }
-  }
-  for (int k = tid; k < m; k += 256) {
-    double d = R[k * LDR + k];
-    if (!(d > 0.0) || !isfinite(d)) atomicOr(&s_bad, 1);
-  }
-  redv[tid] = off;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (tid < s) redv[tid] = fmax(redv[tid], redv[tid + s]);
-    __syncthreads();
-  }
-  off = redv[0];
-  if (tid == 0) atomic_max_nonneg(&st->max_off_bits, isfinite(off) ? off : 1.0e300);
-  if (s_bad) {
-    if (tid == 0) {
-      rotflag[p] = 0;
-      atomicOr(&st->breakdown, 1);
-    }
-    return;
-  }
-  if (off <= tol) {
-    if (tid == 0) rotflag[p] = 0;
-    return;
-  }
-
-  // 3. Cholesky A_P = R^T R (upper R), right-looking
-  for (int k = 0; k < m; k++) {
-    if (tid == 0) {
-      double d = R[k * LDR + k];
-      if (d > 0.0 && isfinite(d)) {
-        s_piv = sqrt(d);
-      } else {
-        s_piv = 0.0;
-        s_bad = 1;
-      }
-    }
-    __syncthreads();
-    if (s_bad) break;
-    const double piv = s_piv;
-    for (int c = k + 1 + tid; c < m; c += 256) R[c * LDR + k] /= piv;
-    if (tid == 0) R[k * LDR + k] = piv;
-    __syncthreads();
-    const int L = m - k - 1;
-    for (int e = tid; e < L * L; e += 256) {
-      int r = k + 1 + e / L, c = k + 1 + e % L;
-      if (r <= c) R[c * LDR + r] -= R[r * LDR + k] * R[c * LDR + k];
-    }
-    __syncthreads();
-  }
-  if (s_bad) {
-    if (tid == 0) {
-      rotflag[p] = 0;
-      atomicOr(&st->breakdown, 1);
-    }
-    return;
-  }
-  for (int e = tid; e < kMaxPivot * kMaxPivot; e += 256) {
-    int r = e >> 6, c = e & 63;
-    if (r < m && c < m) {
-      if (r > c) R[c * LDR + r] = 0.0;
-      W[c * LDR + r] = (r == c) ? 1.0 : 0.0;
-    }
-  }
-  __syncthreads();
-
-  // 4. inner one-sided J-Jacobi on the columns of R, accumulating W_P
-  const int slot = tid >> 3, sub = tid & 7;
-  const int mp = m + (m & 1);
-  const int n1 = nfirst[p], n2 = m - n1;
-  const int L = max(n1, n2);
-  const int nsweeps = inner_mode == 0 ? inner_max : 1;
-  const int nrounds = inner_mode == 0 ? mp - 1 : L;
-  for (int it = 0; it < nsweeps; it++) {
-    if (tid == 0) s_cnt = 0;
-    __syncthreads();
-    for (int q = 0; q < nrounds; q++) {
-      int r = -1, s = -1;
-      if (inner_mode == 0) {
-        if (slot < mp / 2) {
-          int a = slot == 0 ? 0 : ((slot - 1 + q) % (mp - 1)) + 1;
-          int b = ((mp - 1 - slot - 1 + q) % (mp - 1)) + 1;
-          r = min(a, b);
-          s = max(a, b);
-        }
-      } else if (slot < L) {
-        int k2 = (slot + q) % L;
-        if (slot < n1 && k2 < n2) {
-          r = slot;
-          s = n1 + k2;
-        }
-      }
-      if (r >= 0 && s < m) {
-        double* Rr = R + r * LDR;
-        double* Rs = R + s * LDR;
-        double arr = 0.0, ass = 0.0, ars = 0.0;
-        for (int i = sub; i < m; i += 8) {
-          double x = Rr[i], y = Rs[i];
-          arr += x * x;
-          ass += y * y;
-          ars += x * y;
-        }
-#pragma unroll
-        for (int msk = 1; msk < 8; msk <<= 1) {
-          arr += __shfl_xor(arr, msk);
-          ass += __shfl_xor(ass, msk);
-          ars += __shfl_xor(ars, msk);
-        }
-        double sigma = (double)(sg[r] * sg[s]);
-        double cs = 1.0, sn = 0.0;
-        int rc = rot_params(arr, ass, ars, sigma, tol, &cs, &sn);
-        if (rc > 0) {
-          double* Wr = W + r * LDR;
-          double* Ws = W + s * LDR;
-          for (int i = sub; i < m; i += 8) {
-            double x = Rr[i], y = Rs[i];
-            Rr[i] = cs * x - sigma * sn * y;
-            Rs[i] = sn * x + cs * y;
-            double u = Wr[i], w = Ws[i];
-            Wr[i] = cs * u - sigma * sn * w;
-            Ws[i] = sn * u + cs * w;
-          }
-          if (sub == 0) atomicAdd(&s_cnt, 1);
-        } else if (rc < 0 && sub == 0) {
-          atomicOr(&s_bad, 1);
-        }
-      }
-      __syncthreads();
-    }
-    const int cnt = s_cnt;
-    if (tid == 0) {
-      s_total += cnt;
-      s_sweeps++;
-    }
-    __syncthreads();
-    if (cnt == 0) break;
-  }
-  if (tid == 0) {
-    atomicAdd(&st->rotations, (unsigned long long)s_total);
-    atomicAdd(&st->inner_sweeps, (unsigned long long)s_sweeps);
-    atomicAdd(&st->pivot_cols, (unsigned long long)m);
-    atomicAdd(&st->pivot_cols3, (unsigned long long)m * m * m);
-  }
-  if (s_bad && tid == 0) atomicOr(&st->breakdown, 1);
-
-  // 5. W_P out
-  const int rotated = s_total > 0;
-  if (rotated) {
-    double* Wo = Wout + (size_t)p * (kMaxPivot * kMaxPivot);
-    for (int e = tid; e < kMaxPivot * kMaxPivot; e += 256) {
-      int c = e >> 6, r = e & 63;
-      if (r < m && c < m) Wo[c * kMaxPivot + r] = W[c * LDR + r];
-    }
-  }
-  if (tid == 0) {
-    rotflag[p] = rotated;
-    if (rotated) atomicAdd(&st->pivots_rotated, 1);
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Update [G_i G_j] <- [G_i G_j] W_P in place.  Grid (nch, P), 256 threads.
 // Computed transposed, D^T = W_P^T X^T, so that each lane's results are
 // consecutive rows of one column (coalesced stores).  A wave loads its whole
 // 16-row strip (all m columns) before writing any of it.
 // ---------------------------------------------------------------------------
+constexpr int LDR = kMaxPivot + 1;
 constexpr int LDW = kMaxPivot + 1;
 
 __global__ __launch_bounds__(256) void k_update_f64(double* __restrict__ G, int ldg, int n,
@@ -489,235 +249,6 @@ __global__ __launch_bounds__(256) void k_gram_c128(const double* __restrict__ G,
         }
         t++;
       }
-  }
-}
-
-// Pivot solve, complex.  R and W_P in LDS as interleaved complex, leading
-// dimension 65.  The rotation carries the phase e^{i alpha} = a_rs / eta on
-// column r (the modified rotation of eq. 2.3 used by Algorithm 3.1).
-__global__ __launch_bounds__(256) void k_pivot_c128(const double* __restrict__ part, int nch,
-                                                    const int* __restrict__ mlist, const int* __restrict__ nfirst,
-                                                    const signed char* __restrict__ sgl, double tol, int inner_max,
-                                                    int inner_mode, double* __restrict__ Wout,
-                                                    int* __restrict__ rotflag, SweepStats* st) {
-  __shared__ double2 R[kMaxPivot * LDR];
-  __shared__ double2 W[kMaxPivot * LDR];
-  __shared__ double redv[256];
-  __shared__ int s_cnt, s_bad, s_total, s_sweeps;
-  __shared__ double s_piv;
-  const int p = blockIdx.x, tid = threadIdx.x;
-  const int m = mlist[p];
-  const signed char* sg = sgl + p * kMaxPivot;
-
-  const double2* P = reinterpret_cast<const double2*>(part) + (size_t)p * nch * (kMaxPivot * kMaxPivot);
-  for (int e = tid; e < kMaxPivot * kMaxPivot; e += 256) {
-    int r = e >> 6, c = e & 63;
-    if (r < m && c < m && (r >> 4) <= (c >> 4)) {
-      double sr = 0.0, si = 0.0;
-      for (int k = 0; k < nch; k++) {
-        double2 v = P[(size_t)k * (kMaxPivot * kMaxPivot) + e];
-        sr += v.x;
-        si += v.y;
-      }
-      R[c * LDR + r] = double2{sr, si};
-    }
-  }
-  if (tid == 0) {
-    s_bad = 0;
-    s_total = 0;
-    s_sweeps = 0;
-  }
-  __syncthreads();
-  for (int e = tid; e < kMaxPivot * kMaxPivot; e += 256) {
-    int r = e >> 6, c = e & 63;
-    if (r < m && c < m && r > c) {
-      double2 u = R[r * LDR + c];
-      R[c * LDR + r] = double2{u.x, -u.y};
-    }
-  }
-  __syncthreads();
-  // the diagonal of a Hermitian matrix is real
-  for (int k = tid; k < m; k += 256) R[k * LDR + k].y = 0.0;
-  __syncthreads();
-
-  double off = 0.0;
-  for (int e = tid; e < kMaxPivot * kMaxPivot; e += 256) {
-    int r = e >> 6, c = e & 63;
-    if (r < m && c < m && r < c) {
-      double2 a = R[c * LDR + r];
-      double v = hypot(a.x, a.y) / (sqrt(R[r * LDR + r].x) * sqrt(R[c * LDR + c].x));
-      off = fmax(off, v);
-    }
-  }
-  for (int k = tid; k < m; k += 256) {
-    double d = R[k * LDR + k].x;
-    if (!(d > 0.0) || !isfinite(d)) atomicOr(&s_bad, 1);
-  }
-  redv[tid] = off;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (tid < s) redv[tid] = fmax(redv[tid], redv[tid + s]);
-    __syncthreads();
-  }
-  off = redv[0];
-  if (tid == 0) atomic_max_nonneg(&st->max_off_bits, isfinite(off) ? off : 1.0e300);
-  if (s_bad) {
-    if (tid == 0) {
-      rotflag[p] = 0;
-      atomicOr(&st->breakdown, 1);
-    }
-    return;
-  }
-  if (off <= tol) {
-    if (tid == 0) rotflag[p] = 0;
-    return;
-  }
-
-  // Cholesky A_P = R^H R
-  for (int k = 0; k < m; k++) {
-    if (tid == 0) {
-      double d = R[k * LDR + k].x;
-      if (d > 0.0 && isfinite(d)) {
-        s_piv = sqrt(d);
-      } else {
-        s_piv = 0.0;
-        s_bad = 1;
-      }
-    }
-    __syncthreads();
-    if (s_bad) break;
-    const double piv = s_piv;
-    for (int c = k + 1 + tid; c < m; c += 256) {
-      double2 a = R[c * LDR + k];
-      R[c * LDR + k] = double2{a.x / piv, a.y / piv};
-    }
-    if (tid == 0) R[k * LDR + k] = double2{piv, 0.0};
-    __syncthreads();
-    const int L = m - k - 1;
-    for (int e = tid; e < L * L; e += 256) {
-      int r = k + 1 + e / L, c = k + 1 + e % L;
-      if (r <= c) {
-        double2 u = R[r * LDR + k], v = R[c * LDR + k], a = R[c * LDR + r];
-        // a -= conj(u) v
-        a.x -= u.x * v.x + u.y * v.y;
-        a.y -= u.x * v.y - u.y * v.x;
-        R[c * LDR + r] = a;
-      }
-    }
-    __syncthreads();
-  }
-  if (s_bad) {
-    if (tid == 0) {
-      rotflag[p] = 0;
-      atomicOr(&st->breakdown, 1);
-    }
-    return;
-  }
-  for (int e = tid; e < kMaxPivot * kMaxPivot; e += 256) {
-    int r = e >> 6, c = e & 63;
-    if (r < m && c < m) {
-      if (r > c) R[c * LDR + r] = double2{0.0, 0.0};
-      W[c * LDR + r] = double2{(r == c) ? 1.0 : 0.0, 0.0};
-    }
-  }
-  __syncthreads();
-
-  const int slot = tid >> 3, sub = tid & 7;
-  const int mp = m + (m & 1);
-  const int n1 = nfirst[p], n2 = m - n1;
-  const int L = max(n1, n2);
-  const int nsweeps = inner_mode == 0 ? inner_max : 1;
-  const int nrounds = inner_mode == 0 ? mp - 1 : L;
-  for (int it = 0; it < nsweeps; it++) {
-    if (tid == 0) s_cnt = 0;
-    __syncthreads();
-    for (int q = 0; q < nrounds; q++) {
-      int r = -1, s = -1;
-      if (inner_mode == 0) {
-        if (slot < mp / 2) {
-          int a = slot == 0 ? 0 : ((slot - 1 + q) % (mp - 1)) + 1;
-          int b = ((mp - 1 - slot - 1 + q) % (mp - 1)) + 1;
-          r = min(a, b);
-          s = max(a, b);
-        }
-      } else if (slot < L) {
-        int k2 = (slot + q) % L;
-        if (slot < n1 && k2 < n2) {
-          r = slot;
-          s = n1 + k2;
-        }
-      }
-      if (r >= 0 && s < m) {
-        double2* Rr = R + r * LDR;
-        double2* Rs = R + s * LDR;
-        double arr = 0.0, ass = 0.0, are = 0.0, aim = 0.0;
-        for (int i = sub; i < m; i += 8) {
-          double2 x = Rr[i], y = Rs[i];
-          arr += x.x * x.x + x.y * x.y;
-          ass += y.x * y.x + y.y * y.y;
-          are += x.x * y.x + x.y * y.y;  // conj(x) y
-          aim += x.x * y.y - x.y * y.x;
-        }
-#pragma unroll
-        for (int msk = 1; msk < 8; msk <<= 1) {
-          arr += __shfl_xor(arr, msk);
-          ass += __shfl_xor(ass, msk);
-          are += __shfl_xor(are, msk);
-          aim += __shfl_xor(aim, msk);
-        }
-        const double sigma = (double)(sg[r] * sg[s]);
-        const double aabs = hypot(are, aim);
-        // eta = sgn(Re a_rs) |a_rs| is real; the 2x2 problem on [e^{ia} g_r, g_s] is real
-        const double eta = (are < 0.0 ? -1.0 : 1.0) * aabs;
-        double cs = 1.0, sn = 0.0;
-        int rc = rot_params(arr, ass, eta, sigma, tol, &cs, &sn);
-        if (rc > 0) {
-          const double pr = are / eta, pi = aim / eta;  // e^{i alpha}
-          double2* Wr = W + r * LDR;
-          double2* Ws = W + s * LDR;
-          for (int i = sub; i < m; i += 8) {
-            double2 x = Rr[i], y = Rs[i];
-            double fr = pr * x.x - pi * x.y, fi = pr * x.y + pi * x.x;
-            Rr[i] = double2{cs * fr - sigma * sn * y.x, cs * fi - sigma * sn * y.y};
-            Rs[i] = double2{sn * fr + cs * y.x, sn * fi + cs * y.y};
-            double2 u = Wr[i], w = Ws[i];
-            double gr = pr * u.x - pi * u.y, gi = pr * u.y + pi * u.x;
-            Wr[i] = double2{cs * gr - sigma * sn * w.x, cs * gi - sigma * sn * w.y};
-            Ws[i] = double2{sn * gr + cs * w.x, sn * gi + cs * w.y};
-          }
-          if (sub == 0) atomicAdd(&s_cnt, 1);
-        } else if (rc < 0 && sub == 0) {
-          atomicOr(&s_bad, 1);
-        }
-      }
-      __syncthreads();
-    }
-    const int cnt = s_cnt;
-    if (tid == 0) {
-      s_total += cnt;
-      s_sweeps++;
-    }
-    __syncthreads();
-    if (cnt == 0) break;
-  }
-  if (tid == 0) {
-    atomicAdd(&st->rotations, (unsigned long long)s_total);
-    atomicAdd(&st->inner_sweeps, (unsigned long long)s_sweeps);
-    atomicAdd(&st->pivot_cols, (unsigned long long)m);
-    atomicAdd(&st->pivot_cols3, (unsigned long long)m * m * m);
-  }
-  if (s_bad && tid == 0) atomicOr(&st->breakdown, 1);
-  const int rotated = s_total > 0;
-  if (rotated) {
-    double2* Wo = reinterpret_cast<double2*>(Wout) + (size_t)p * (kMaxPivot * kMaxPivot);
-    for (int e = tid; e < kMaxPivot * kMaxPivot; e += 256) {
-      int c = e >> 6, r = e & 63;
-      if (r < m && c < m) Wo[c * kMaxPivot + r] = W[c * LDR + r];
-    }
-  }
-  if (tid == 0) {
-    rotflag[p] = rotated;
-    if (rotated) atomicAdd(&st->pivots_rotated, 1);
   }
 }
 
@@ -870,12 +401,6 @@ void launch_gram_f64(const double* G, int ldg, int n, const PivotList& pl, int n
                      rows_per_chunk, part);
 }
 
-void launch_pivot_f64(const double* part, int nch, const PivotList& pl, double tol, int inner_max,
-                      int inner_mode, double* W, int* rotflag, SweepStats* st, hipStream_t stream) {
-  hipLaunchKernelGGL(k_pivot_f64, dim3(pl.count), dim3(256), 0, stream, part, nch, pl.m, pl.nfirst, pl.sg, tol,
-                     inner_max, inner_mode, W, rotflag, st);
-}
-
 void launch_update_f64(double* G, int ldg, int n, const PivotList& pl, const double* W, const int* rotflag,
                        int rows_per_chunk, hipStream_t stream) {
   int nch = (n + rows_per_chunk - 1) / rows_per_chunk;
@@ -887,12 +412,6 @@ void launch_gram_c128(const double* G, int ldg, int n, const PivotList& pl, int 
                       double* part, hipStream_t stream) {
   hipLaunchKernelGGL(k_gram_c128, dim3(nch, pl.count), dim3(256), 0, stream, G, ldg, n, pl.cols, pl.m,
                      rows_per_chunk, part);
-}
-
-void launch_pivot_c128(const double* part, int nch, const PivotList& pl, double tol, int inner_max,
-                       int inner_mode, double* W, int* rotflag, SweepStats* st, hipStream_t stream) {
-  hipLaunchKernelGGL(k_pivot_c128, dim3(pl.count), dim3(256), 0, stream, part, nch, pl.m, pl.nfirst, pl.sg, tol,
-                     inner_max, inner_mode, W, rotflag, st);
 }
 
 void launch_update_c128(double* G, int ldg, int n, const PivotList& pl, const double* W, const int* rotflag,

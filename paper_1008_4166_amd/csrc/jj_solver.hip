@@ -24,7 +24,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/jjacobi.h"
+#include "jjacobi.h"
 #include "jj_device.h"
 
 namespace jj {
@@ -290,7 +290,7 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
   Plan P = make_plan(n, J, nt, o.strategy);
   const int h = std::max(P.npairs_max, 1);
   // chunking of the row dimension for the Gram and update kernels
-  int nch = std::max(1, std::min((1024 + h - 1) / h, (n + 63) / 64));
+  int nch = std::max(1, std::min(std::min((1024 + h - 1) / h, (n + 63) / 64), kMaxChunks));
   int rows_g = ((n + nch - 1) / nch + 63) / 64 * 64;
   nch = (n + rows_g - 1) / rows_g;
   int rows_u = 256;
@@ -411,8 +411,9 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
       // Block-oriented variant (Section 5.3): the first step of a sweep makes one
       // full pass over its pivots (covering every diagonal block), the other
       // steps one pass over the off-diagonal block only.
-      const int mode = (o.inner_mode == 1 && t > 0) ? 1 : 0;
-      const int imax = o.inner_mode == 1 ? 1 : inner_max;
+      const bool block_oriented = o.inner_mode == 0;
+      const int mode = (block_oriented && t > 0) ? 1 : 0;  // kernel mode 1: off-diagonal pass only
+      const int imax = block_oriented ? 1 : inner_max;
       e0 = prof.mark();
       gram(G, ldg, n, pl, nch, rows_g, d_part, stream);
       prof.done(JJ_K_GRAM, e0, pl.count);
