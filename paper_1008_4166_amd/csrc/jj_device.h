@@ -11,7 +11,7 @@ constexpr int kMaxPivot = 64;
 // Largest block width.
 constexpr int kMaxBlock = kMaxPivot / 2;
 // Largest number of row chunks of one Gram block (partials summed by the pivot solver).
-constexpr int kMaxChunks = 16;
+constexpr int kMaxChunks = 8;
 
 // Device-side counters of one sweep.
 struct SweepStats {

@@ -56,14 +56,25 @@ __global__ __launch_bounds__(256) void k_gram_f64(const double* __restrict__ G, 
 #pragma unroll
   for (int t = 0; t < 10; t++) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
 
-  for (int base = r0 + wave * 16; base < r1; base += 64) {
-    double x[4][4];
+  // software pipeline: the loads of the next 16-row group are in flight while
+  // the MFMAs of the current group run
+  double x[4][4], xn[4][4];
+  int base = r0 + wave * 16;
+#pragma unroll
+  for (int J = 0; J < 4; J++)
+#pragma unroll
+    for (int kk = 0; kk < 4; kk++) {
+      int row = base + 4 * g + kk;
+      x[J][kk] = (cp[J] != nullptr && row < r1) ? cp[J][row] : 0.0;
+    }
+  for (; base < r1; base += 64) {
+    const int nb = base + 64;
 #pragma unroll
     for (int J = 0; J < 4; J++)
 #pragma unroll
       for (int kk = 0; kk < 4; kk++) {
-        int row = base + 4 * g + kk;
-        x[J][kk] = (cp[J] != nullptr && row < r1) ? cp[J][row] : 0.0;
+        int row = nb + 4 * g + kk;
+        xn[J][kk] = (cp[J] != nullptr && row < r1) ? cp[J][row] : 0.0;
       }
 #pragma unroll
     for (int kk = 0; kk < 4; kk++) {
@@ -76,6 +87,10 @@ __global__ __launch_bounds__(256) void k_gram_f64(const double* __restrict__ G, 
           t++;
         }
     }
+#pragma unroll
+    for (int J = 0; J < 4; J++)
+#pragma unroll
+      for (int kk = 0; kk < 4; kk++) x[J][kk] = xn[J][kk];
   }
   // fixed-order reduction of the four waves: (w0 + w2) + (w1 + w3)
   if (wave >= 2)
@@ -136,15 +151,23 @@ __global__ __launch_bounds__(256) void k_update_f64(double* __restrict__ G, int 
 
   const int r0 = ch * rows_per_chunk;
   const int r1 = min(n, r0 + rows_per_chunk);
-  for (int row0 = r0 + wave * 16; row0 < r1; row0 += 64) {
-    const int row = row0 + c16;
-    double x[16];
+  int pcol[16];
 #pragma unroll
-    for (int kk = 0; kk < 16; kk++) {
-      int c = 4 * kk + g;
-      int pc = scol[c];
-      x[kk] = (kk < ks && pc >= 0 && row < r1) ? G[(size_t)pc * ldg + row] : 0.0;
-    }
+  for (int kk = 0; kk < 16; kk++) pcol[kk] = scol[4 * kk + g];
+  // the next strip's loads are issued before the current strip's MFMAs
+  double x[16], xn[16];
+  int row0 = r0 + wave * 16;
+#pragma unroll
+  for (int kk = 0; kk < 16; kk++) {
+    const int row = row0 + c16;
+    x[kk] = (kk < ks && pcol[kk] >= 0 && row < r1) ? G[(size_t)pcol[kk] * ldg + row] : 0.0;
+  }
+  for (; row0 < r1; row0 += 64) {
+    const int row = row0 + c16;
+    const int nrow = row + 64;
+#pragma unroll
+    for (int kk = 0; kk < 16; kk++)
+      xn[kk] = (kk < ks && pcol[kk] >= 0 && nrow < r1) ? G[(size_t)pcol[kk] * ldg + nrow] : 0.0;
 #pragma unroll
     for (int I = 0; I < 4; I++) {
       if (I < nt) {
@@ -160,6 +183,8 @@ __global__ __launch_bounds__(256) void k_update_f64(double* __restrict__ G, int 
         }
       }
     }
+#pragma unroll
+    for (int kk = 0; kk < 16; kk++) x[kk] = xn[kk];
   }
 }
 

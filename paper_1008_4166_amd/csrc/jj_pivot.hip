@@ -128,10 +128,11 @@ __device__ __forceinline__ double dpp_f64(double v) {
 // pairs quad 0 with quad 1 of each 8-lane half: three DPP steps, no LDS.
 template <int LPS>
 __device__ __forceinline__ double slot_sum(double v) {
-  if constexpr (LPS == 8) {
+  if constexpr (LPS == 8 || LPS == 16) {
     v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
     v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
-    v += dpp_f64<0x141>(v);  // row_half_mirror
+    v += dpp_f64<0x141>(v);  // row_half_mirror: quad 0 <-> quad 1 of each 8-lane half
+    if constexpr (LPS == 16) v += dpp_f64<0x140>(v);  // row_mirror: half 0 <-> half 1 of the row
     return v;
   } else {
 #pragma unroll
@@ -175,12 +176,15 @@ __global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ p
   __shared__ double redv[NT];
   __shared__ __align__(16) T rowb[kMaxPivot];
   __shared__ int s_cnt, s_bad;
+  __shared__ signed char s_sg[kMaxPivot];
+  __shared__ int ring_sg[2][32];
   T* R = lds;
   T* W = lds + kMaxPivot * LDR;
   const int p = blockIdx.x, tid = threadIdx.x;
   const int m = mlist[p];
   const int n1 = nfirst[p], n2 = m - n1;
-  const signed char* sg = sgl + p * kMaxPivot;
+  if (tid < kMaxPivot) s_sg[tid] = sgl[p * kMaxPivot + tid];
+  const signed char* sg = s_sg;  // signs of the pivot's columns, in LDS
 
   // ---- 1. A_P = sum of the chunk partials (upper 16x16 tiles), Hermitian fill ----
   // all chunk loads of an element are issued before the (fixed-order) sum
@@ -254,9 +258,13 @@ __global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ p
       for (int c = 0; c < kMaxPivot; c++) a[c] = (i < m && c < m) ? R[c * LDR + i] : zero_of(T());
       double mydiag = 1.0;
       for (int k = 0; k < m; k++) {
-        if (i == k) {
+        if (i == k) {  // publish the part of row k right of column k (16-column groups)
 #pragma unroll
-          for (int c = 0; c < kMaxPivot; c++) rowbuf[c] = a[c];
+          for (int g = 0; g < kMaxPivot / 16; g++)
+            if (16 * g + 15 >= k) {
+#pragma unroll
+              for (int c = 0; c < 16; c++) rowbuf[16 * g + c] = a[16 * g + c];
+            }
         }
         wave_sync();
         const double d = real_of(rowbuf[k]);
@@ -389,8 +397,10 @@ __global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ p
       T* ring0 = lds;
       T* ring1 = lds + 2 * 32 * kMaxPivot;  // each ring: 2 x 32 slots x 64 rows of T
       const double sr = have_r ? (double)sg[slot] : 0.0;
+      double ss = slot < n2 ? (double)sg[n1 + slot] : 0.0;  // sign of the held second-block column
       for (int q = 0; q < L; q++) {
-        const int sidx = (slot + q) % L;  // second-block column held by this slot
+        int sidx = slot + q;  // second-block column held by this slot: (slot + q) mod L
+        if (sidx >= L) sidx -= L;
         if (slot < L && have_r && sidx < n2) {
           double arr = 0.0, ass = 0.0, are = 0.0, aim = 0.0;
 #pragma unroll
@@ -403,7 +413,7 @@ __global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ p
           ass = slot_sum<LPS>(ass);
           are = slot_sum<LPS>(are);
           if (CPLX) aim = slot_sum<LPS>(aim);
-          const double sigma = sr * (double)sg[n1 + sidx];
+          const double sigma = sr * ss;
           double cs, sn, pr, pi;
           int rc = pair_rotation(arr, ass, are, aim, CPLX, sigma, tol, &cs, &sn, &pr, &pi);
           if (rc > 0) {
@@ -426,6 +436,7 @@ __global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ p
           // ring holds 16-byte elements (two reals or one complex) so that each
           // lane moves its share with 128-bit LDS accesses
           double2* ring = reinterpret_cast<double2*>((q & 1) ? ring1 : ring0);
+          if (slot < L && sub == 0) ring_sg[q & 1][slot] = (int)ss;
           if (slot < L) {
             if constexpr (CPLX) {
 #pragma unroll
@@ -443,7 +454,8 @@ __global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ p
           }
           __syncthreads();
           if (slot < L) {
-            const int from = (slot + 1) % L;
+            const int from = slot + 1 < L ? slot + 1 : 0;
+            ss = (double)ring_sg[q & 1][from];
             if constexpr (CPLX) {
 #pragma unroll
               for (int j = 0; j < RPL; j++) {
