@@ -124,6 +124,7 @@ def main():
     ap.add_argument("--block-width", type=int, default=32)
     ap.add_argument("--inner-mode", type=int, default=0)
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the solver runs on a single MI355X; "
@@ -215,6 +216,29 @@ def main():
                                   gbytes_per_launch=wk[k]["bytes"] / 1e9 if k in wk else None)
                           for k in ("gram", "pivot", "update", "final", "other")}
         out["inner"] = dict(rotations=pr["rotations"], inner_sweeps=pr["inner_sweeps"])
+    # mixed-precision form (FP32-MFMA Gram in pre-sweeps, FP64 rotations, W_P and update)
+    if not args.no_mixed:
+        mopts = jj.make_opts(stream=stream, block_width=args.block_width, inner_mode=args.inner_mode, precision=1)
+        mwork = [pristine.clone() for _ in range(K)]
+        minfos = []
+        torch.cuda.synchronize()
+        t0m = time.perf_counter()
+        for i in range(K):
+            info = jj.jj_info()
+            st = jj.jjacobi_solve_ex(jj.JJ_F64, mwork[i].data_ptr(), J, n, n, lam.data_ptr(), Vt.data_ptr(), n, 0.0,
+                                     0, mopts, info)
+            if st != 0:
+                raise RuntimeError("mixed solve status %d" % st)
+            minfos.append(info.as_dict())
+        torch.cuda.synchronize()
+        dtm = time.perf_counter() - t0m
+        lam_m = lam.cpu().numpy()
+        macc = {"vs_fp64_gpu_max_rel": float(np.max(np.abs(lam_m - lam_h) / np.abs(lam_h)))}
+        if ref is not None:
+            macc["vs_oracle_max_rel"] = float(np.max(np.abs(lam_m - ref) / np.abs(ref)))
+        out["mixed"] = dict(value=n * K / dtm, ms_per_step=dtm / K * 1e3, sweeps=[i["sweeps"] for i in minfos],
+                            mixed_sweeps=[i["mixed_sweeps"] for i in minfos], accuracy=macc,
+                            speedup_vs_fp64=ms_step / (dtm / K * 1e3))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n, oracle_sweeps if oracle_sweeps else 14)
     print(json.dumps(out), flush=True)

@@ -20,7 +20,7 @@ struct SweepStats {
   int breakdown;                    // Cholesky / hyperbolic-rotation failure seen
   int nonfinite;                    // non-finite value seen in G
   int zero_col;                     // final column norm zero
-  int pad;
+  int soft_fail;                    // pivot that could not be factored in a mixed-precision sweep
   unsigned long long rotations;     // plane rotations applied by pivot solves
   unsigned long long inner_sweeps;  // inner sweeps run by pivot solves
   unsigned long long pivot_cols;    // sum of m over pivots that ran the inner solve
@@ -48,13 +48,22 @@ void launch_gram_f64(const double* G, int ldg, int n, const PivotList& pl, int n
 void launch_gram_c128(const double* G, int ldg, int n, const PivotList& pl, int nch, int rows_per_chunk,
                       double* part, hipStream_t stream);
 
+// Same partials formed on FP32 MFMA from FP64 data converted on load (mixed-
+// precision pre-sweeps); the output is FP64 in the same layout.
+void launch_gram_f32mix(const double* G, int ldg, int n, const PivotList& pl, int nch, int rows_per_chunk,
+                        double* part, hipStream_t stream);
+void launch_gram_c64mix(const double* G, int ldg, int n, const PivotList& pl, int nch, int rows_per_chunk,
+                        double* part, hipStream_t stream);
+
 // Per pivot: sum the Gram partials, test convergence, Cholesky, inner one-sided
 // J-Jacobi on R accumulating W_P.  W[p] (kMaxPivot x kMaxPivot, column-major,
 // complex interleaved for c128) and rotflag[p] are written.
+// soft = 1 (mixed-precision sweeps): a pivot whose Gram block cannot be factored
+// is left untouched and counted in soft_fail instead of raising breakdown.
 void launch_pivot_f64(const double* part, int nch, const PivotList& pl, double tol, int inner_max,
-                      int inner_mode, double* W, int* rotflag, SweepStats* st, hipStream_t stream);
+                      int inner_mode, int soft, double* W, int* rotflag, SweepStats* st, hipStream_t stream);
 void launch_pivot_c128(const double* part, int nch, const PivotList& pl, double tol, int inner_max,
-                       int inner_mode, double* W, int* rotflag, SweepStats* st, hipStream_t stream);
+                       int inner_mode, int soft, double* W, int* rotflag, SweepStats* st, hipStream_t stream);
 
 // [G_i G_j] <- [G_i G_j] W_P in place for pivots with rotflag set.
 void launch_update_f64(double* G, int ldg, int n, const PivotList& pl, const double* W, const int* rotflag,

@@ -346,6 +346,7 @@ __global__ void k_reset_stats(SweepStats* st) {
     st->breakdown = 0;
     st->nonfinite = 0;
     st->zero_col = 0;
+    st->soft_fail = 0;
     st->rotations = 0ull;
     st->inner_sweeps = 0ull;
     st->pivot_cols = 0ull;

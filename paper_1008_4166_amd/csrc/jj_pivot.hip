@@ -167,8 +167,8 @@ template <bool CPLX, int LPS>
 __global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ part, int nch,
                                                     const int* __restrict__ mlist, const int* __restrict__ nfirst,
                                                     const signed char* __restrict__ sgl, double tol, int inner_max,
-                                                    int mode, double* __restrict__ Wout, int* __restrict__ rotflag,
-                                                    SweepStats* st) {
+                                                    int mode, int soft, double* __restrict__ Wout,
+                                                    int* __restrict__ rotflag, SweepStats* st) {
   typedef typename Scalar<CPLX>::T T;
   constexpr int NT = 32 * LPS;
   constexpr int RPL = kMaxPivot / LPS;  // rows of one column held by a lane
@@ -237,7 +237,7 @@ __global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ p
   if (s_bad || off <= tol) {
     if (tid == 0) {
       rotflag[p] = 0;
-      if (s_bad) atomicOr(&st->breakdown, 1);
+      if (s_bad) atomicOr(soft ? &st->soft_fail : &st->breakdown, 1);
     }
     return;
   }
@@ -306,7 +306,7 @@ __global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ p
     if (s_bad) {
       if (tid == 0) {
         rotflag[p] = 0;
-        atomicOr(&st->breakdown, 1);
+        atomicOr(soft ? &st->soft_fail : &st->breakdown, 1);
       }
       return;
     }
@@ -503,7 +503,7 @@ __global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ p
     if (c_all == 0) break;
     __syncthreads();
   }
-  if (s_bad && tid == 0) atomicOr(&st->breakdown, 1);
+  if (s_bad && tid == 0) atomicOr(soft ? &st->soft_fail : &st->breakdown, 1);
 
   // ---- 5. W_P out ----
   const int rotated = total > 0;
@@ -527,15 +527,15 @@ __global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ p
 constexpr int kPivotLPS = 8;
 
 void launch_pivot_f64(const double* part, int nch, const PivotList& pl, double tol, int inner_max, int inner_mode,
-                      double* W, int* rotflag, SweepStats* st, hipStream_t stream) {
+                      int soft, double* W, int* rotflag, SweepStats* st, hipStream_t stream) {
   hipLaunchKernelGGL((k_pivot<false, kPivotLPS>), dim3(pl.count), dim3(32 * kPivotLPS), 0, stream, part, nch, pl.m,
-                     pl.nfirst, pl.sg, tol, inner_max, inner_mode, W, rotflag, st);
+                     pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st);
 }
 
 void launch_pivot_c128(const double* part, int nch, const PivotList& pl, double tol, int inner_max, int inner_mode,
-                       double* W, int* rotflag, SweepStats* st, hipStream_t stream) {
+                       int soft, double* W, int* rotflag, SweepStats* st, hipStream_t stream) {
   hipLaunchKernelGGL((k_pivot<true, kPivotLPS>), dim3(pl.count), dim3(32 * kPivotLPS), 0, stream, part, nch, pl.m,
-                     pl.nfirst, pl.sg, tol, inner_max, inner_mode, W, rotflag, st);
+                     pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st);
 }
 
 }  // namespace jj

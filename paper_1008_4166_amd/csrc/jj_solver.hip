@@ -378,10 +378,18 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
     return JJ_NONFINITE;
   }
 
-  auto gram = cplx ? launch_gram_c128 : launch_gram_f64;
+  auto gram64 = cplx ? launch_gram_c128 : launch_gram_f64;
+  auto gram32 = cplx ? launch_gram_c64mix : launch_gram_f32mix;
   auto pivot = cplx ? launch_pivot_c128 : launch_pivot_f64;
   auto update = cplx ? launch_update_c128 : launch_update_f64;
 
+  // Mixed precision: sweeps run with the FP32-MFMA Gram until a sweep's largest
+  // scaled off-diagonal falls below mixed_switch; those sweeps use a rotation
+  // threshold above FP32 rounding noise and never declare convergence.
+  bool mixed = o.precision == 1;
+  const double mix_switch = o.mixed_switch > 0.0 ? o.mixed_switch : 1e-5;
+  const double tol_mix = std::max(tol, std::ldexp(1.0, -20));
+  int mixed_sweeps = 0;
   int status = JJ_NOT_CONVERGED, sweep = 0;
   long long piv_rot = 0;
   double last_off = 0.0;
@@ -389,6 +397,9 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
   if (P.nbl < 2) status = JJ_OK;
   while (P.nbl >= 2 && sweep < max_sweeps) {
     sweep++;
+    const bool use_mix = mixed;
+    auto gram = use_mix ? gram32 : gram64;
+    const double stol = use_mix ? tol_mix : tol;
     e0 = prof.mark();
     launch_reset_stats(d_st, stream);
     prof.done(JJ_K_OTHER, e0, 0);
@@ -398,7 +409,7 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
       gram(G, ldg, n, dl, nch, rows_g, d_part, stream);
       prof.done(JJ_K_GRAM, e0, dl.count);
       e0 = prof.mark();
-      pivot(d_part, nch, dl, tol, inner_max, 0, d_W, d_rot, d_st, stream);
+      pivot(d_part, nch, dl, stol, inner_max, 0, use_mix, d_W, d_rot, d_st, stream);
       prof.done(JJ_K_PIVOT, e0, dl.count);
       e0 = prof.mark();
       update(G, ldg, n, dl, d_W, d_rot, rows_u, stream);
@@ -418,7 +429,7 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
       gram(G, ldg, n, pl, nch, rows_g, d_part, stream);
       prof.done(JJ_K_GRAM, e0, pl.count);
       e0 = prof.mark();
-      pivot(d_part, nch, pl, tol, imax, mode, d_W, d_rot, d_st, stream);
+      pivot(d_part, nch, pl, stol, imax, mode, use_mix, d_W, d_rot, d_st, stream);
       prof.done(JJ_K_PIVOT, e0, pl.count);
       e0 = prof.mark();
       update(G, ldg, n, pl, d_W, d_rot, rows_u, stream);
@@ -440,6 +451,14 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
     if (hst.breakdown) {
       breakdown = true;
       break;
+    }
+    if (use_mix) {
+      // leave FP32 Gram blocks once they are accurate enough to finish in FP64, or
+      // when some pivot's FP32 Gram block could not be factored (its scaled
+      // condition number exceeds what FP32 resolves)
+      mixed_sweeps++;
+      if (off < mix_switch || hst.pivots_rotated == 0 || hst.soft_fail) mixed = false;
+      continue;
     }
     if (hst.pivots_rotated == 0) {
       status = JJ_OK;
@@ -477,7 +496,7 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
     info->pivots_rotated = piv_rot;
     info->final_offdiag = last_off;
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    info->mixed_sweeps = 0;
+    info->mixed_sweeps = mixed_sweeps;
   }
   return status;
 }

@@ -186,3 +186,16 @@ def test_full_size_against_stored_oracle(k):
         assert rel_err(lg, ldf) <= 4 * rel_err(ref, ldf)
     # inertia, prescribed spectrum within conditioning
     assert np.sum(lg > 0) == np.sum(J > 0)
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("n,lo,hi", [(64, 1e-3, 1e3), (200, 1e-6, 1.0), (300, 1e-12, 1.0)])
+def test_mixed_precision_reaches_fp64_accuracy(cplx, n, lo, hi):
+    # FP32-MFMA Gram in the pre-sweeps, FP64 rotations / W_P / update throughout,
+    # FP64 finishing sweeps: the same parity bar as the plain FP64 path
+    G, J, lam = jjgen.make(n, cplx, (3 * n) // 7, lo, hi, seed=600 + n)
+    lg, V, info = gpu_solve(G, J, precision=1)
+    assert info["status"] == 0
+    assert info["mixed_sweeps"] >= 1
+    check_parity(G, J, lg, "mixed n=%d cplx=%s" % (n, cplx))
+    check_vectors(G, J, lg, V)
