@@ -103,6 +103,79 @@ def cpu_baseline(n_full, sweeps_full):
                 sweep_seconds_sample=dt, status_sample=r["status"])
 
 
+def bench_batched(jj, torch, count, loop_sample):
+    """Mixed-size batch: `count` matrices, n ~ U{16..512}, half real float64 and
+    half complex128, inertia ~ U{0..n}, |lambda| log-uniform in [1e-6, 1e3].
+    One jjacobi_solve_batched call (graph-replayed device step loop) against a
+    loop of single jjacobi_solve_ex calls on an evenly spaced sample."""
+    import ctypes
+
+    import jjgen
+    specs = jjgen.batch_recipe(count=count)
+    t = time.perf_counter()
+    flat, offs, Js, lams_pres = jjgen.make_batch(specs)
+    gen_s = time.perf_counter() - t
+    dev = torch.device("cuda:0")
+    pristine = torch.from_numpy(flat).to(dev)
+    work = torch.empty_like(pristine)
+    vbuf = torch.empty_like(pristine)
+    ns = [s["n"] for s in specs]
+    loff = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
+    lam = torch.empty(int(loff[-1]), dtype=torch.float64, device=dev)
+    dts = [1 if s["cplx"] else 0 for s in specs]
+    base, vbase, lbase = work.data_ptr(), vbuf.data_ptr(), lam.data_ptr()
+    Gp = [base + 8 * int(o) for o in offs[:-1]]
+    Vp = [vbase + 8 * int(o) for o in offs[:-1]]
+    Lp = [lbase + 8 * int(o) for o in loff[:-1]]
+    stream = torch.cuda.current_stream().cuda_stream
+    opts = jj.make_opts(stream=stream)
+    infos = (jj.jj_info * count)()
+
+    def run():
+        work.copy_(pristine)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = jj.jjacobi_solve_batched(count, dts, Gp, Js, ns, ns, Lp, Vp, ns, 0.0, 0, opts, infos)
+        torch.cuda.synchronize()
+        return st, time.perf_counter() - t0
+
+    st_warm, dt_warm = run()  # includes the block-width autotuning of each size bucket
+    st, dt = run()
+    statuses = [infos[k].status for k in range(count)]
+    sweeps = [infos[k].sweeps for k in range(count)]
+    # invariants of every result: Sylvester inertia and trace(H) = sum_i j_i ||g_i||^2
+    lam_h = lam.cpu().numpy()
+    inertia_bad, tr_err = 0, 0.0
+    for k in range(count):
+        lk = lam_h[loff[k]:loff[k + 1]]
+        inertia_bad += int(np.sum(lk > 0) != np.sum(Js[k] > 0))
+        g = flat[offs[k]:offs[k + 1]]
+        col2 = (np.abs(g.view(np.complex128)) ** 2 if specs[k]["cplx"] else g * g).reshape(ns[k], ns[k]).sum(axis=1)
+        tr = float(np.sum(Js[k].astype(float) * col2))
+        tr_err = max(tr_err, abs(float(np.sum(lk)) - tr) / float(np.sum(np.abs(lk))))
+        pres = np.sort(lams_pres[k])[::-1]
+    # loop of single solves on an evenly spaced sample, scaled to the whole batch
+    idx = list(range(0, count, max(1, count // max(1, loop_sample))))[:loop_sample]
+    work.copy_(pristine)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in idx:
+        info = jj.jj_info()
+        jj.jjacobi_solve_ex(dts[k], Gp[k], Js[k], ns[k], ns[k], Lp[k], Vp[k], ns[k], 0.0, 0, opts, info)
+    torch.cuda.synchronize()
+    dt_loop = (time.perf_counter() - t0) * count / len(idx)
+    return dict(metric="batched mats/s", value=count / dt, unit="mats/s", seconds=dt, count=count,
+                worst_status=st, status_counts={str(v): statuses.count(v) for v in set(statuses)},
+                sweeps_max=max(sweeps), sweeps_mean=float(np.mean(sweeps)),
+                loop_of_single_solves=dict(value=count / dt_loop, unit="mats/s", sample=len(idx),
+                                           seconds_scaled=dt_loop),
+                speedup_vs_loop=dt_loop / dt, first_call_seconds_with_tuning=dt_warm,
+                invariants=dict(inertia_mismatches=inertia_bad, max_trace_rel_err=tr_err),
+                gen_seconds=gen_s, gbytes=flat.nbytes / 1e9,
+                workload="4096 matrices, n ~ U{16..512}, half float64 half complex128, p ~ U{0..n}, "
+                         "|lambda| log-uniform [1e-6, 1e3]" if count == 4096 else "batch of %d" % count)
+
+
 def stored_oracle(k):
     path = os.path.join(ROOT, "tests", "golden", "config%d_lambda_double.txt" % k)
     if not os.path.exists(path):
@@ -125,6 +198,9 @@ def main():
     ap.add_argument("--inner-mode", type=int, default=0)
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--loop-sample", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the solver runs on a single MI355X; "
@@ -239,6 +315,8 @@ def main():
         out["mixed"] = dict(value=n * K / dtm, ms_per_step=dtm / K * 1e3, sweeps=[i["sweeps"] for i in minfos],
                             mixed_sweeps=[i["mixed_sweeps"] for i in minfos], accuracy=macc,
                             speedup_vs_fp64=ms_step / (dtm / K * 1e3))
+    if not args.no_batched:
+        out["batched"] = bench_batched(jj, torch, args.batch_count, args.loop_sample)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n, oracle_sweeps if oracle_sweeps else 14)
     print(json.dumps(out), flush=True)

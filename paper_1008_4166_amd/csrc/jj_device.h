@@ -39,37 +39,93 @@ struct PivotList {
   int count;
 };
 
+// Optional batch descriptor.  A launch over S slots serves many independent
+// problems at once: slot s belongs to problem slot_prob[s] and handles pair
+// slot_k[s] of that problem's current step.  The problem's step, its active
+// flag and its sweep counters live in device memory, so a sequence of steps can
+// run (and be captured in a graph) without the host.  slot_prob == nullptr
+// means a single-problem launch: slot s is pivot s of the tables, G / ldg / n
+// come from the kernel arguments and the counters from `st`.
+struct Batch {
+  const int* slot_prob = nullptr;
+  const int* slot_k = nullptr;
+  const int* tab_base = nullptr;  // [problems] first pivot-table entry of step 0
+  const int* npairs = nullptr;    // [problems] pairs per step
+  const int* step = nullptr;      // [problems] current step
+  const int* active = nullptr;    // [problems] 1 while being solved
+  double* const* gptr = nullptr;  // [problems] G
+  const int* ldg = nullptr;       // [problems]
+  const int* nrow = nullptr;      // [problems] rows (= order)
+  SweepStats* st = nullptr;       // [problems] counters of the current sweep
+  const double* tol = nullptr;    // [problems] rotation threshold
+};
+
+// Resolve a launch slot: pivot-table index, matrix, rows and counters.
+// Returns false for slots of problems that are not active.
+__device__ __forceinline__ bool batch_resolve(const Batch& b, int slot, int& pidx, double*& G, int& ldg, int& n,
+                                              SweepStats*& st) {
+  if (b.slot_prob == nullptr) {
+    pidx = slot;
+    return true;
+  }
+  const int i = b.slot_prob[slot];
+  if (!b.active[i]) return false;
+  pidx = b.tab_base[i] + b.step[i] * b.npairs[i] + b.slot_k[slot];
+  G = b.gptr[i];
+  ldg = b.ldg[i];
+  n = b.nrow[i];
+  st = b.st + i;
+  return true;
+}
+
 // ---- launchers (all asynchronous on `stream`) ----
 
 // part[p][ch][r*64 + c] = sum over rows of chunk ch of conj(G[row, col(r)]) G[row, col(c)],
 // for the upper 16x16 tiles (tile(r) <= tile(c)).  Real: FP64 MFMA.
 void launch_gram_f64(const double* G, int ldg, int n, const PivotList& pl, int nch, int rows_per_chunk,
-                     double* part, hipStream_t stream);
+                     double* part, hipStream_t stream, const Batch& b = Batch());
 void launch_gram_c128(const double* G, int ldg, int n, const PivotList& pl, int nch, int rows_per_chunk,
-                      double* part, hipStream_t stream);
+                      double* part, hipStream_t stream, const Batch& b = Batch());
 
 // Same partials formed on FP32 MFMA from FP64 data converted on load (mixed-
 // precision pre-sweeps); the output is FP64 in the same layout.
 void launch_gram_f32mix(const double* G, int ldg, int n, const PivotList& pl, int nch, int rows_per_chunk,
-                        double* part, hipStream_t stream);
+                        double* part, hipStream_t stream, const Batch& b = Batch());
 void launch_gram_c64mix(const double* G, int ldg, int n, const PivotList& pl, int nch, int rows_per_chunk,
-                        double* part, hipStream_t stream);
+                        double* part, hipStream_t stream, const Batch& b = Batch());
 
 // Per pivot: sum the Gram partials, test convergence, Cholesky, inner one-sided
 // J-Jacobi on R accumulating W_P.  W[p] (kMaxPivot x kMaxPivot, column-major,
 // complex interleaved for c128) and rotflag[p] are written.
 // soft = 1 (mixed-precision sweeps): a pivot whose Gram block cannot be factored
 // is left untouched and counted in soft_fail instead of raising breakdown.
-void launch_pivot_f64(const double* part, int nch, const PivotList& pl, double tol, int inner_max,
-                      int inner_mode, int soft, double* W, int* rotflag, SweepStats* st, hipStream_t stream);
-void launch_pivot_c128(const double* part, int nch, const PivotList& pl, double tol, int inner_max,
-                       int inner_mode, int soft, double* W, int* rotflag, SweepStats* st, hipStream_t stream);
+// mode: 0 full inner sweeps (inner_max), 1 off-diagonal pass only, 2 (batched
+// block-oriented) full pass at step 0 of the problem's sweep, else off-diagonal.
+// Only the first ceil(n / rows_per_chunk) partials of a pivot are summed.
+void launch_pivot_f64(const double* part, int nch, int n, int rows_per_chunk, const PivotList& pl, double tol,
+                      int inner_max, int inner_mode, int soft, double* W, int* rotflag, SweepStats* st,
+                      hipStream_t stream, const Batch& b = Batch());
+void launch_pivot_c128(const double* part, int nch, int n, int rows_per_chunk, const PivotList& pl, double tol,
+                       int inner_max, int inner_mode, int soft, double* W, int* rotflag, SweepStats* st,
+                       hipStream_t stream, const Batch& b = Batch());
 
 // [G_i G_j] <- [G_i G_j] W_P in place for pivots with rotflag set.
+// nch_u: number of row chunks in the grid (0: ceil(n / rows_per_chunk)).
 void launch_update_f64(double* G, int ldg, int n, const PivotList& pl, const double* W, const int* rotflag,
-                       int rows_per_chunk, hipStream_t stream);
+                       int rows_per_chunk, hipStream_t stream, const Batch& b = Batch(), int nch_u = 0);
 void launch_update_c128(double* G, int ldg, int n, const PivotList& pl, const double* W,
-                        const int* rotflag, int rows_per_chunk, hipStream_t stream);
+                        const int* rotflag, int rows_per_chunk, hipStream_t stream, const Batch& b = Batch(),
+                        int nch_u = 0);
+
+// Batched bookkeeping (one thread or one workgroup per problem).
+void launch_batch_advance(int count, const int* nsteps, int* step, int* sweep, int* active, int* status,
+                          SweepStats* st, double* final_off, int max_sweeps, int* active_count, hipStream_t stream);
+void launch_batch_check_finite(int count, double* const* gptr, const int* ldg, const int* nrow, const int* width,
+                               int* bad, hipStream_t stream);
+void launch_batch_finalize(int count, double* const* gptr, const int* ldg, const int* nrow, const int* width,
+                           const int* colmap, const int* cm_off, const signed char* sgn, double* const* lam_ptr,
+                           double* const* v_ptr, const int* ldv, double* dwork, int* rkwork, int* zero_col,
+                           hipStream_t stream);
 
 void launch_reset_stats(SweepStats* st, hipStream_t stream);
 void launch_check_finite(const double* G, int ldg, int n, int cplx, SweepStats* st, hipStream_t stream);

@@ -25,11 +25,17 @@ __device__ __forceinline__ f4 mfma16f(float a, float b, f4 c) {
 }
 
 // Real: same grid, row grouping and output format as the FP64 Gram kernel.
-__global__ __launch_bounds__(256) void k_gram_f32mix(const double* __restrict__ G, int ldg, int n,
+__global__ __launch_bounds__(256) void k_gram_f32mix(const double* __restrict__ G0, int ldg0, int n0,
                                                      const int* __restrict__ cols, const int* __restrict__ mlist,
-                                                     int rows_per_chunk, double* __restrict__ part) {
+                                                     int rows_per_chunk, double* __restrict__ part, Batch bt) {
   __shared__ d4m red[10][64];
-  const int p = blockIdx.y, ch = blockIdx.x, nch = gridDim.x;
+  const int slot = blockIdx.y, ch = blockIdx.x, nch = gridDim.x;
+  int p = slot, ldg = ldg0, n = n0;
+  double* Gm = const_cast<double*>(G0);
+  SweepStats* stp = nullptr;
+  if (!batch_resolve(bt, slot, p, Gm, ldg, n, stp)) return;
+  if (ch > 0 && ch * rows_per_chunk >= n) return;  // chunk beyond this problem's rows
+  const double* G = Gm;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int c16 = lane & 15, g = lane >> 4;
   const int m = mlist[p];
@@ -94,7 +100,7 @@ __global__ __launch_bounds__(256) void k_gram_f32mix(const double* __restrict__ 
     __syncthreads();
   }
   if (wave == 0) {
-    double* out = part + ((size_t)p * nch + ch) * (kMaxPivot * kMaxPivot);
+    double* out = part + ((size_t)slot * nch + ch) * (kMaxPivot * kMaxPivot);
     int t = 0;
 #pragma unroll
     for (int I = 0; I < 4; I++)
@@ -110,11 +116,17 @@ __global__ __launch_bounds__(256) void k_gram_f32mix(const double* __restrict__ 
 }
 
 // Complex: Re A = Xr^T Xr + Xi^T Xi, Im A = Xr^T Xi - Xi^T Xr on FP32 MFMA.
-__global__ __launch_bounds__(256) void k_gram_c64mix(const double* __restrict__ G, int ldg, int n,
+__global__ __launch_bounds__(256) void k_gram_c64mix(const double* __restrict__ G0, int ldg0, int n0,
                                                      const int* __restrict__ cols, const int* __restrict__ mlist,
-                                                     int rows_per_chunk, double* __restrict__ part) {
+                                                     int rows_per_chunk, double* __restrict__ part, Batch bt) {
   __shared__ d4m red[10][2][64];
-  const int p = blockIdx.y, ch = blockIdx.x, nch = gridDim.x;
+  const int slot = blockIdx.y, ch = blockIdx.x, nch = gridDim.x;
+  int p = slot, ldg = ldg0, n = n0;
+  double* Gm = const_cast<double*>(G0);
+  SweepStats* stp = nullptr;
+  if (!batch_resolve(bt, slot, p, Gm, ldg, n, stp)) return;
+  if (ch > 0 && ch * rows_per_chunk >= n) return;  // chunk beyond this problem's rows
+  const double* G = Gm;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int c16 = lane & 15, g = lane >> 4;
   const int m = mlist[p];
@@ -181,7 +193,7 @@ __global__ __launch_bounds__(256) void k_gram_c64mix(const double* __restrict__ 
     __syncthreads();
   }
   if (wave == 0) {
-    double* out = part + ((size_t)p * nch + ch) * (2 * kMaxPivot * kMaxPivot);
+    double* out = part + ((size_t)slot * nch + ch) * (2 * kMaxPivot * kMaxPivot);
     int t = 0;
 #pragma unroll
     for (int I = 0; I < 4; I++)
@@ -201,15 +213,15 @@ __global__ __launch_bounds__(256) void k_gram_c64mix(const double* __restrict__ 
 }
 
 void launch_gram_f32mix(const double* G, int ldg, int n, const PivotList& pl, int nch, int rows_per_chunk,
-                        double* part, hipStream_t stream) {
+                        double* part, hipStream_t stream, const Batch& b) {
   hipLaunchKernelGGL(k_gram_f32mix, dim3(nch, pl.count), dim3(256), 0, stream, G, ldg, n, pl.cols, pl.m,
-                     rows_per_chunk, part);
+                     rows_per_chunk, part, b);
 }
 
 void launch_gram_c64mix(const double* G, int ldg, int n, const PivotList& pl, int nch, int rows_per_chunk,
-                        double* part, hipStream_t stream) {
+                        double* part, hipStream_t stream, const Batch& b) {
   hipLaunchKernelGGL(k_gram_c64mix, dim3(nch, pl.count), dim3(256), 0, stream, G, ldg, n, pl.cols, pl.m,
-                     rows_per_chunk, part);
+                     rows_per_chunk, part, b);
 }
 
 }  // namespace jj

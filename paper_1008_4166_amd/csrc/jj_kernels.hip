@@ -33,11 +33,17 @@ __device__ __forceinline__ void atomic_max_nonneg(unsigned long long* addr, doub
 // are rows {4g + kk}.  All upper tiles (I <= J) of the 64x64 partial are
 // accumulated; the four waves are reduced through LDS in a fixed order.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_gram_f64(const double* __restrict__ G, int ldg, int n,
+__global__ __launch_bounds__(256) void k_gram_f64(const double* __restrict__ G0, int ldg0, int n0,
                                                   const int* __restrict__ cols, const int* __restrict__ mlist,
-                                                  int rows_per_chunk, double* __restrict__ part) {
+                                                  int rows_per_chunk, double* __restrict__ part, Batch bt) {
   __shared__ d4 red[2][10][64];
-  const int p = blockIdx.y, ch = blockIdx.x, nch = gridDim.x;
+  const int slot = blockIdx.y, ch = blockIdx.x, nch = gridDim.x;
+  int p = slot, ldg = ldg0, n = n0;
+  double* Gm = const_cast<double*>(G0);
+  SweepStats* stp = nullptr;
+  if (!batch_resolve(bt, slot, p, Gm, ldg, n, stp)) return;
+  if (ch > 0 && ch * rows_per_chunk >= n) return;  // chunk beyond this problem's rows
+  const double* G = Gm;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int c16 = lane & 15, g = lane >> 4;
   const int m = mlist[p];
@@ -103,7 +109,7 @@ __global__ __launch_bounds__(256) void k_gram_f64(const double* __restrict__ G, 
     for (int t = 0; t < 10; t++) red[0][t][lane] = acc[t];
   __syncthreads();
   if (wave == 0) {
-    double* out = part + ((size_t)p * nch + ch) * (kMaxPivot * kMaxPivot);
+    double* out = part + ((size_t)slot * nch + ch) * (kMaxPivot * kMaxPivot);
     int t = 0;
 #pragma unroll
     for (int I = 0; I < 4; I++)
@@ -128,12 +134,17 @@ __global__ __launch_bounds__(256) void k_gram_f64(const double* __restrict__ G, 
 constexpr int LDR = kMaxPivot + 1;
 constexpr int LDW = kMaxPivot + 1;
 
-__global__ __launch_bounds__(256) void k_update_f64(double* __restrict__ G, int ldg, int n,
+__global__ __launch_bounds__(256) void k_update_f64(double* __restrict__ G0, int ldg0, int n0,
                                                     const int* __restrict__ cols, const int* __restrict__ mlist,
                                                     const double* __restrict__ Wg, const int* __restrict__ rotflag,
-                                                    int rows_per_chunk) {
-  const int p = blockIdx.y, ch = blockIdx.x;
-  if (!rotflag[p]) return;
+                                                    int rows_per_chunk, Batch bt) {
+  const int slot = blockIdx.y, ch = blockIdx.x;
+  int p = slot, ldg = ldg0, n = n0;
+  double* G = G0;
+  SweepStats* stp = nullptr;
+  if (!batch_resolve(bt, slot, p, G, ldg, n, stp)) return;
+  if (!rotflag[slot]) return;
+  if (ch * rows_per_chunk >= n) return;
   __shared__ double Ws[kMaxPivot * LDW];
   __shared__ int scol[kMaxPivot];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -141,7 +152,7 @@ __global__ __launch_bounds__(256) void k_update_f64(double* __restrict__ G, int 
   const int m = mlist[p];
   const int nt = (m + 15) >> 4;   // output column tiles
   const int ks = (m + 3) >> 2;    // k-steps of 4 columns
-  const double* Wp = Wg + (size_t)p * (kMaxPivot * kMaxPivot);
+  const double* Wp = Wg + (size_t)slot * (kMaxPivot * kMaxPivot);
   for (int e = tid; e < kMaxPivot * kMaxPivot; e += 256) {
     int c = e >> 6, r = e & 63;
     Ws[c * LDW + r] = (r < m && c < m) ? Wp[c * kMaxPivot + r] : 0.0;
@@ -192,11 +203,17 @@ __global__ __launch_bounds__(256) void k_update_f64(double* __restrict__ G, int 
 // Complex Hermitian (complex128, interleaved).  A = X^H X is formed from real
 // MFMA products: Re A = Xr^T Xr + Xi^T Xi, Im A = Xr^T Xi - Xi^T Xr.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_gram_c128(const double* __restrict__ G, int ldg, int n,
+__global__ __launch_bounds__(256) void k_gram_c128(const double* __restrict__ G0, int ldg0, int n0,
                                                    const int* __restrict__ cols, const int* __restrict__ mlist,
-                                                   int rows_per_chunk, double* __restrict__ part) {
+                                                   int rows_per_chunk, double* __restrict__ part, Batch bt) {
   __shared__ d4 red[10][2][64];
-  const int p = blockIdx.y, ch = blockIdx.x, nch = gridDim.x;
+  const int slot = blockIdx.y, ch = blockIdx.x, nch = gridDim.x;
+  int p = slot, ldg = ldg0, n = n0;
+  double* Gm = const_cast<double*>(G0);
+  SweepStats* stp = nullptr;
+  if (!batch_resolve(bt, slot, p, Gm, ldg, n, stp)) return;
+  if (ch > 0 && ch * rows_per_chunk >= n) return;  // chunk beyond this problem's rows
+  const double* G = Gm;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int c16 = lane & 15, g = lane >> 4;
   const int m = mlist[p];
@@ -258,7 +275,7 @@ __global__ __launch_bounds__(256) void k_gram_c128(const double* __restrict__ G,
     __syncthreads();
   }
   if (wave == 0) {
-    double* out = part + ((size_t)p * nch + ch) * (2 * kMaxPivot * kMaxPivot);
+    double* out = part + ((size_t)slot * nch + ch) * (2 * kMaxPivot * kMaxPivot);
     int t = 0;
 #pragma unroll
     for (int I = 0; I < 4; I++)
@@ -279,12 +296,17 @@ __global__ __launch_bounds__(256) void k_gram_c128(const double* __restrict__ G,
 
 // Update, complex: D^T = W^T X^T with Re = Wr^T Xr^T - Wi^T Xi^T and
 // Im = Wi^T Xr^T + Wr^T Xi^T.
-__global__ __launch_bounds__(256) void k_update_c128(double* __restrict__ G, int ldg, int n,
+__global__ __launch_bounds__(256) void k_update_c128(double* __restrict__ G0, int ldg0, int n0,
                                                      const int* __restrict__ cols, const int* __restrict__ mlist,
                                                      const double* __restrict__ Wg, const int* __restrict__ rotflag,
-                                                     int rows_per_chunk) {
-  const int p = blockIdx.y, ch = blockIdx.x;
-  if (!rotflag[p]) return;
+                                                     int rows_per_chunk, Batch bt) {
+  const int slot = blockIdx.y, ch = blockIdx.x;
+  int p = slot, ldg = ldg0, n = n0;
+  double* G = G0;
+  SweepStats* stp = nullptr;
+  if (!batch_resolve(bt, slot, p, G, ldg, n, stp)) return;
+  if (!rotflag[slot]) return;
+  if (ch * rows_per_chunk >= n) return;
   __shared__ double2 Ws[kMaxPivot * LDW];
   __shared__ int scol[kMaxPivot];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -292,7 +314,7 @@ __global__ __launch_bounds__(256) void k_update_c128(double* __restrict__ G, int
   const int m = mlist[p];
   const int nt = (m + 15) >> 4;
   const int ks = (m + 3) >> 2;
-  const double2* Wp = reinterpret_cast<const double2*>(Wg) + (size_t)p * (kMaxPivot * kMaxPivot);
+  const double2* Wp = reinterpret_cast<const double2*>(Wg) + (size_t)slot * (kMaxPivot * kMaxPivot);
   for (int e = tid; e < kMaxPivot * kMaxPivot; e += 256) {
     int c = e >> 6, r = e & 63;
     Ws[c * LDW + r] = (r < m && c < m) ? Wp[c * kMaxPivot + r] : double2{0.0, 0.0};
@@ -422,29 +444,29 @@ __global__ __launch_bounds__(256) void k_write_v(const double* __restrict__ G, i
 // launchers
 // ---------------------------------------------------------------------------
 void launch_gram_f64(const double* G, int ldg, int n, const PivotList& pl, int nch, int rows_per_chunk,
-                     double* part, hipStream_t stream) {
+                     double* part, hipStream_t stream, const Batch& b) {
   hipLaunchKernelGGL(k_gram_f64, dim3(nch, pl.count), dim3(256), 0, stream, G, ldg, n, pl.cols, pl.m,
-                     rows_per_chunk, part);
+                     rows_per_chunk, part, b);
 }
 
 void launch_update_f64(double* G, int ldg, int n, const PivotList& pl, const double* W, const int* rotflag,
-                       int rows_per_chunk, hipStream_t stream) {
-  int nch = (n + rows_per_chunk - 1) / rows_per_chunk;
+                       int rows_per_chunk, hipStream_t stream, const Batch& b, int nch_u) {
+  int nch = nch_u > 0 ? nch_u : (n + rows_per_chunk - 1) / rows_per_chunk;
   hipLaunchKernelGGL(k_update_f64, dim3(nch, pl.count), dim3(256), 0, stream, G, ldg, n, pl.cols, pl.m, W,
-                     rotflag, rows_per_chunk);
+                     rotflag, rows_per_chunk, b);
 }
 
 void launch_gram_c128(const double* G, int ldg, int n, const PivotList& pl, int nch, int rows_per_chunk,
-                      double* part, hipStream_t stream) {
+                      double* part, hipStream_t stream, const Batch& b) {
   hipLaunchKernelGGL(k_gram_c128, dim3(nch, pl.count), dim3(256), 0, stream, G, ldg, n, pl.cols, pl.m,
-                     rows_per_chunk, part);
+                     rows_per_chunk, part, b);
 }
 
 void launch_update_c128(double* G, int ldg, int n, const PivotList& pl, const double* W, const int* rotflag,
-                        int rows_per_chunk, hipStream_t stream) {
-  int nch = (n + rows_per_chunk - 1) / rows_per_chunk;
+                        int rows_per_chunk, hipStream_t stream, const Batch& b, int nch_u) {
+  int nch = nch_u > 0 ? nch_u : (n + rows_per_chunk - 1) / rows_per_chunk;
   hipLaunchKernelGGL(k_update_c128, dim3(nch, pl.count), dim3(256), 0, stream, G, ldg, n, pl.cols, pl.m, W,
-                     rotflag, rows_per_chunk);
+                     rotflag, rows_per_chunk, b);
 }
 
 void launch_reset_stats(SweepStats* st, hipStream_t stream) {

@@ -164,11 +164,12 @@ __device__ __forceinline__ int pair_rotation(double arr, double ass, double are,
 }
 
 template <bool CPLX, int LPS>
-__global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ part, int nch,
-                                                    const int* __restrict__ mlist, const int* __restrict__ nfirst,
+__global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ part, int nch, int n0,
+                                                    int rows_per_chunk, const int* __restrict__ mlist,
+                                                    const int* __restrict__ nfirst,
                                                     const signed char* __restrict__ sgl, double tol, int inner_max,
                                                     int mode, int soft, double* __restrict__ Wout,
-                                                    int* __restrict__ rotflag, SweepStats* st) {
+                                                    int* __restrict__ rotflag, SweepStats* st0, Batch bt) {
   typedef typename Scalar<CPLX>::T T;
   constexpr int NT = 32 * LPS;
   constexpr int RPL = kMaxPivot / LPS;  // rows of one column held by a lane
@@ -180,7 +181,18 @@ __global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ p
   __shared__ int ring_sg[2][32];
   T* R = lds;
   T* W = lds + kMaxPivot * LDR;
-  const int p = blockIdx.x, tid = threadIdx.x;
+  const int bslot = blockIdx.x, tid = threadIdx.x;
+  int p = bslot, n = n0, ldg_unused = 0;
+  double* G_unused = nullptr;
+  SweepStats* st = st0;
+  if (!batch_resolve(bt, bslot, p, G_unused, ldg_unused, n, st)) return;
+  // partials present for this pivot's rows (fewer than nch for short problems in a batch)
+  const int nchp = min(nch, (n + rows_per_chunk - 1) / rows_per_chunk);
+  if (bt.slot_prob != nullptr) {
+    const int prob = bt.slot_prob[bslot];
+    tol = bt.tol[prob];
+    if (mode == 2) mode = (bt.step[prob] == 0) ? 0 : 1;  // block-oriented, per problem
+  }
   const int m = mlist[p];
   const int n1 = nfirst[p], n2 = m - n1;
   if (tid < kMaxPivot) s_sg[tid] = sgl[p * kMaxPivot + tid];
@@ -188,14 +200,14 @@ __global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ p
 
   // ---- 1. A_P = sum of the chunk partials (upper 16x16 tiles), Hermitian fill ----
   // all chunk loads of an element are issued before the (fixed-order) sum
-  const T* P = reinterpret_cast<const T*>(part) + (size_t)p * nch * (kMaxPivot * kMaxPivot);
+  const T* P = reinterpret_cast<const T*>(part) + (size_t)bslot * nch * (kMaxPivot * kMaxPivot);
   for (int e = tid; e < kMaxPivot * kMaxPivot; e += NT) {
     int r = e >> 6, c = e & 63;
     if (r < m && c < m && (r >> 4) <= (c >> 4)) {
       T v[kMaxChunks];
 #pragma unroll
       for (int k = 0; k < kMaxChunks; k++)
-        v[k] = k < nch ? P[(size_t)k * (kMaxPivot * kMaxPivot) + e] : zero_of(T());
+        v[k] = k < nchp ? P[(size_t)k * (kMaxPivot * kMaxPivot) + e] : zero_of(T());
       T s = v[0];
 #pragma unroll
       for (int k = 1; k < kMaxChunks; k++) s = lin2(1.0, s, 1.0, v[k]);
@@ -236,7 +248,7 @@ __global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ p
   if (tid == 0) atomic_max_nonneg(&st->max_off_bits, isfinite(off) ? off : 1.0e300);
   if (s_bad || off <= tol) {
     if (tid == 0) {
-      rotflag[p] = 0;
+      rotflag[bslot] = 0;
       if (s_bad) atomicOr(soft ? &st->soft_fail : &st->breakdown, 1);
     }
     return;
@@ -305,7 +317,7 @@ __global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ p
     __syncthreads();
     if (s_bad) {
       if (tid == 0) {
-        rotflag[p] = 0;
+        rotflag[bslot] = 0;
         atomicOr(soft ? &st->soft_fail : &st->breakdown, 1);
       }
       return;
@@ -508,14 +520,14 @@ __global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ p
   // ---- 5. W_P out ----
   const int rotated = total > 0;
   if (rotated) {
-    T* Wo = reinterpret_cast<T*>(Wout) + (size_t)p * (kMaxPivot * kMaxPivot);
+    T* Wo = reinterpret_cast<T*>(Wout) + (size_t)bslot * (kMaxPivot * kMaxPivot);
     for (int e = tid; e < kMaxPivot * kMaxPivot; e += NT) {
       int c = e >> 6, r = e & 63;
       if (r < m && c < m) Wo[c * kMaxPivot + r] = W[c * LDR + r];
     }
   }
   if (tid == 0) {
-    rotflag[p] = rotated;
+    rotflag[bslot] = rotated;
     if (rotated) atomicAdd(&st->pivots_rotated, 1);
     atomicAdd(&st->rotations, (unsigned long long)total);
     atomicAdd(&st->inner_sweeps, (unsigned long long)sweeps_run);
@@ -526,16 +538,18 @@ __global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ p
 
 constexpr int kPivotLPS = 8;
 
-void launch_pivot_f64(const double* part, int nch, const PivotList& pl, double tol, int inner_max, int inner_mode,
-                      int soft, double* W, int* rotflag, SweepStats* st, hipStream_t stream) {
-  hipLaunchKernelGGL((k_pivot<false, kPivotLPS>), dim3(pl.count), dim3(32 * kPivotLPS), 0, stream, part, nch, pl.m,
-                     pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st);
+void launch_pivot_f64(const double* part, int nch, int n, int rows_per_chunk, const PivotList& pl, double tol,
+                      int inner_max, int inner_mode, int soft, double* W, int* rotflag, SweepStats* st,
+                      hipStream_t stream, const Batch& b) {
+  hipLaunchKernelGGL((k_pivot<false, kPivotLPS>), dim3(pl.count), dim3(32 * kPivotLPS), 0, stream, part, nch, n,
+                     rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st, b);
 }
 
-void launch_pivot_c128(const double* part, int nch, const PivotList& pl, double tol, int inner_max, int inner_mode,
-                       int soft, double* W, int* rotflag, SweepStats* st, hipStream_t stream) {
-  hipLaunchKernelGGL((k_pivot<true, kPivotLPS>), dim3(pl.count), dim3(32 * kPivotLPS), 0, stream, part, nch, pl.m,
-                     pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st);
+void launch_pivot_c128(const double* part, int nch, int n, int rows_per_chunk, const PivotList& pl, double tol,
+                       int inner_max, int inner_mode, int soft, double* W, int* rotflag, SweepStats* st,
+                       hipStream_t stream, const Batch& b) {
+  hipLaunchKernelGGL((k_pivot<true, kPivotLPS>), dim3(pl.count), dim3(32 * kPivotLPS), 0, stream, part, nch, n,
+                     rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st, b);
 }
 
 }  // namespace jj

@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -406,13 +407,13 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
     if (o.diag_pass == 2 || (o.diag_pass == 1 && sweep == 1)) {
       PivotList dl{d_dcols, d_dsg, d_dm, d_dnf, P.nbl};
       e0 = prof.mark();
-      gram(G, ldg, n, dl, nch, rows_g, d_part, stream);
+      gram(G, ldg, n, dl, nch, rows_g, d_part, stream, Batch());
       prof.done(JJ_K_GRAM, e0, dl.count);
       e0 = prof.mark();
-      pivot(d_part, nch, dl, stol, inner_max, 0, use_mix, d_W, d_rot, d_st, stream);
+      pivot(d_part, nch, n, rows_g, dl, stol, inner_max, 0, use_mix, d_W, d_rot, d_st, stream, Batch());
       prof.done(JJ_K_PIVOT, e0, dl.count);
       e0 = prof.mark();
-      update(G, ldg, n, dl, d_W, d_rot, rows_u, stream);
+      update(G, ldg, n, dl, d_W, d_rot, rows_u, stream, Batch(), 0);
       prof.done(JJ_K_UPDATE, e0, 0);
     }
     for (int t = 0; t < P.nsteps; t++) {
@@ -426,13 +427,13 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
       const int mode = (block_oriented && t > 0) ? 1 : 0;  // kernel mode 1: off-diagonal pass only
       const int imax = block_oriented ? 1 : inner_max;
       e0 = prof.mark();
-      gram(G, ldg, n, pl, nch, rows_g, d_part, stream);
+      gram(G, ldg, n, pl, nch, rows_g, d_part, stream, Batch());
       prof.done(JJ_K_GRAM, e0, pl.count);
       e0 = prof.mark();
-      pivot(d_part, nch, pl, stol, imax, mode, use_mix, d_W, d_rot, d_st, stream);
+      pivot(d_part, nch, n, rows_g, pl, stol, imax, mode, use_mix, d_W, d_rot, d_st, stream, Batch());
       prof.done(JJ_K_PIVOT, e0, pl.count);
       e0 = prof.mark();
-      update(G, ldg, n, pl, d_W, d_rot, rows_u, stream);
+      update(G, ldg, n, pl, d_W, d_rot, rows_u, stream, Batch(), 0);
       prof.done(JJ_K_UPDATE, e0, 0);
     }
     ck(hipGetLastError(), "launch");
@@ -499,6 +500,395 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
     info->mixed_sweeps = mixed_sweeps;
   }
   return status;
+}
+
+
+// ---------------------------------------------------------------------------
+// Batched solves.  All problems advance together: one launch per kernel kind
+// covers the current step of every active problem (slots map statically to
+// (problem, pair)); each problem keeps its own step / sweep counters and
+// convergence test on the device (k_batch_advance), so a round of steps needs
+// no host decision and is captured once in a HIP graph and replayed until no
+// problem is active.  Real and complex problems use their own launches.
+// ---------------------------------------------------------------------------
+
+// Autotuner: block width per (dtype, size bucket), chosen by timing two
+// candidate widths on a copy of the first problem of the bucket (two sweeps
+// each) and cached for the process.
+static std::map<std::pair<int, int>, int> g_tuned_bw;
+
+static int size_bucket(int n) {
+  int b = 0;
+  while ((64 << b) < n && b < 12) b++;
+  return b;  // 0: n <= 64, 1: <= 128, 2: <= 256, ...
+}
+
+static int tune_block_width(int dtype, void* G, const signed char* J, int n, int ldg, hipStream_t stream) {
+  const int w = dtype == JJ_C128 ? 2 : 1;
+  if (n <= 64) return 32;  // one pivot holds the whole problem for either width
+  const size_t gsz = (size_t)n * n * w * sizeof(double);
+  double *Gc = nullptr, *lam = nullptr, *V = nullptr;
+  ck(hipMalloc((void**)&Gc, gsz), "hipMalloc tune");
+  ck(hipMalloc((void**)&lam, n * sizeof(double)), "hipMalloc tune");
+  ck(hipMalloc((void**)&V, gsz), "hipMalloc tune");
+  hipEvent_t e0, e1;
+  ck(hipEventCreate(&e0), "event");
+  ck(hipEventCreate(&e1), "event");
+  int best = 32;
+  float best_ms = 1e30f;
+  const int cand[2] = {32, 16};
+  for (int c : cand) {
+    ck(hipMemcpy2DAsync(Gc, (size_t)n * w * sizeof(double), G, (size_t)ldg * w * sizeof(double),
+                        (size_t)n * w * sizeof(double), n, hipMemcpyDeviceToDevice, stream),
+       "copy tune");
+    jj_opts o;
+    jjacobi_default_opts(&o);
+    o.stream = stream;
+    o.block_width = c;
+    ck(hipEventRecord(e0, stream), "event");
+    solve_one(dtype, Gc, J, n, n, lam, V, n, 0.0, 2, o, nullptr);
+    ck(hipEventRecord(e1, stream), "event");
+    ck(hipEventSynchronize(e1), "event");
+    float ms = 0.f;
+    ck(hipEventElapsedTime(&ms, e0, e1), "event");
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipFree(Gc);
+  hipFree(lam);
+  hipFree(V);
+  return best;
+}
+
+static hipStream_t batch_stream() {
+  static hipStream_t s[64] = {};
+  int dev = 0;
+  ck(hipGetDevice(&dev), "hipGetDevice");
+  if (!s[dev & 63]) ck(hipStreamCreateWithFlags(&s[dev & 63], hipStreamNonBlocking), "hipStreamCreate");
+  return s[dev & 63];
+}
+
+struct GroupTables {
+  std::vector<int> cols, m, nfirst, slot_prob, slot_k;
+  std::vector<signed char> sg;
+  int slots = 0, nmax = 0;
+};
+
+static int solve_batch(int count, const int* dtype, void* const* G, const signed char* const* J, const int* n,
+                       const int* ldg, double* const* lambda, void* const* V, const int* ldv, double tol,
+                       int max_sweeps, const jj_opts& o, jj_info* info) {
+  auto t0 = std::chrono::steady_clock::now();
+  hipStream_t caller = (hipStream_t)o.stream;
+  if (max_sweeps <= 0) max_sweeps = 100;
+
+  // block width per problem: fixed by the caller, or tuned per (dtype, size bucket)
+  std::vector<int> bw(count);
+  for (int i = 0; i < count; i++) {
+    if (o.block_width > 0) {
+      bw[i] = std::min(o.block_width, kMaxBlock);
+      continue;
+    }
+    auto key = std::make_pair(dtype[i], size_bucket(n[i]));
+    auto it = g_tuned_bw.find(key);
+    if (it == g_tuned_bw.end())
+      it = g_tuned_bw.emplace(key, tune_block_width(dtype[i], G[i], J[i], n[i], ldg[i], caller)).first;
+    bw[i] = it->second;
+  }
+
+  // per-problem plans; tables concatenated per dtype group
+  std::vector<Plan> plans;
+  plans.reserve(count);
+  GroupTables grp[2];
+  std::vector<int> tab_base(count, 0), npairs(count, 0), nsteps(count, 0), width(count), cm_off(count + 1, 0);
+  std::vector<int> colmap_all;
+  std::vector<signed char> sgn_all;
+  for (int i = 0; i < count; i++) {
+    plans.push_back(make_plan(n[i], J[i], bw[i], o.strategy));
+    const Plan& P = plans.back();
+    const int g = dtype[i] == JJ_C128 ? 1 : 0;
+    width[i] = g ? 2 : 1;
+    cm_off[i + 1] = cm_off[i] + n[i];
+    colmap_all.insert(colmap_all.end(), P.colmap.begin(), P.colmap.end());
+    sgn_all.insert(sgn_all.end(), P.sgn.begin(), P.sgn.end());
+    if (P.nbl < 2 || P.nsteps == 0) continue;
+    GroupTables& T = grp[g];
+    const int h = P.npairs_max;
+    // steps with fewer pairs (modulus pairing) keep m = 0 entries: such slots do nothing
+    tab_base[i] = (int)T.m.size();
+    npairs[i] = h;
+    nsteps[i] = P.nsteps;
+    T.cols.insert(T.cols.end(), P.cols.begin(), P.cols.end());
+    T.sg.insert(T.sg.end(), P.sgp.begin(), P.sgp.end());
+    T.m.insert(T.m.end(), P.m.begin(), P.m.end());
+    T.nfirst.insert(T.nfirst.end(), P.nfirst.begin(), P.nfirst.end());
+    for (int k = 0; k < h; k++) {
+      T.slot_prob.push_back(i);
+      T.slot_k.push_back(k);
+    }
+    T.slots += h;
+    T.nmax = std::max(T.nmax, n[i]);
+  }
+
+  // device workspace
+  int rows_g[2], nch_u[2];
+  for (int g = 0; g < 2; g++) {
+    rows_g[g] = std::max(64, (grp[g].nmax + 63) / 64 * 64);  // one Gram chunk per slot
+    nch_u[g] = std::max(1, (grp[g].nmax + 255) / 256);
+  }
+  Carver c{nullptr};
+  auto layout = [&](Carver& cv, bool fill, std::vector<void*>& ptrs) {
+    auto take = [&](size_t bytes) {
+      void* p = cv.take<char>(bytes);
+      if (fill) ptrs.push_back(p);
+      return p;
+    };
+    for (int g = 0; g < 2; g++) {
+      const GroupTables& T = grp[g];
+      const size_t S = std::max(T.slots, 1);
+      take(std::max<size_t>(T.cols.size(), 1) * sizeof(int));
+      take(std::max<size_t>(T.sg.size(), 1));
+      take(std::max<size_t>(T.m.size(), 1) * sizeof(int));
+      take(std::max<size_t>(T.nfirst.size(), 1) * sizeof(int));
+      take(S * sizeof(int));                                          // slot_prob
+      take(S * sizeof(int));                                          // slot_k
+      take(S * kMaxPivot * kMaxPivot * (g + 1) * sizeof(double));     // partials (one chunk)
+      take(S * kMaxPivot * kMaxPivot * (g + 1) * sizeof(double));     // W
+      take(S * sizeof(int));                                          // rotflag
+    }
+    take(count * sizeof(double*));  // gptr
+    for (int k = 0; k < 9; k++) take(count * sizeof(int));  // ldg nrow width npairs nsteps step sweep active status
+    take(count * sizeof(int));      // tab_base
+    take(count * sizeof(SweepStats));
+    take(count * sizeof(double));   // final_off
+    take(count * sizeof(double));   // tol
+    take(count * sizeof(int));      // bad
+    take(count * sizeof(int));      // zero_col
+    take((count + 1) * sizeof(int));  // cm_off
+    take(std::max<size_t>(colmap_all.size(), 1) * sizeof(int));
+    take(std::max<size_t>(sgn_all.size(), 1));
+    take(count * sizeof(double*));  // lambda ptrs
+    take(count * sizeof(double*));  // V ptrs
+    take(count * sizeof(int));      // ldv
+    take(std::max<size_t>(colmap_all.size(), 1) * sizeof(double));  // dwork
+    take(std::max<size_t>(colmap_all.size(), 1) * sizeof(int));     // rkwork
+    take(sizeof(int));              // active count
+  };
+  std::vector<void*> ptrs;
+  layout(c, false, ptrs);
+  Carver cv{arena_get(c.off + 256)};
+  layout(cv, true, ptrs);
+  size_t pi = 0;
+  struct DevGroup {
+    int *cols, *m, *nfirst, *slot_prob, *slot_k, *rot;
+    signed char* sg;
+    double *part, *W;
+  } dg[2];
+  for (int g = 0; g < 2; g++) {
+    dg[g].cols = (int*)ptrs[pi++];
+    dg[g].sg = (signed char*)ptrs[pi++];
+    dg[g].m = (int*)ptrs[pi++];
+    dg[g].nfirst = (int*)ptrs[pi++];
+    dg[g].slot_prob = (int*)ptrs[pi++];
+    dg[g].slot_k = (int*)ptrs[pi++];
+    dg[g].part = (double*)ptrs[pi++];
+    dg[g].W = (double*)ptrs[pi++];
+    dg[g].rot = (int*)ptrs[pi++];
+  }
+  double** d_gptr = (double**)ptrs[pi++];
+  int* d_ldg = (int*)ptrs[pi++];
+  int* d_nrow = (int*)ptrs[pi++];
+  int* d_width = (int*)ptrs[pi++];
+  int* d_npairs = (int*)ptrs[pi++];
+  int* d_nsteps = (int*)ptrs[pi++];
+  int* d_step = (int*)ptrs[pi++];
+  int* d_sweep = (int*)ptrs[pi++];
+  int* d_active = (int*)ptrs[pi++];
+  int* d_status = (int*)ptrs[pi++];
+  int* d_tab_base = (int*)ptrs[pi++];
+  SweepStats* d_st = (SweepStats*)ptrs[pi++];
+  double* d_final_off = (double*)ptrs[pi++];
+  double* d_tol = (double*)ptrs[pi++];
+  int* d_bad = (int*)ptrs[pi++];
+  int* d_zero = (int*)ptrs[pi++];
+  int* d_cm_off = (int*)ptrs[pi++];
+  int* d_colmap = (int*)ptrs[pi++];
+  signed char* d_sgn = (signed char*)ptrs[pi++];
+  double** d_lam = (double**)ptrs[pi++];
+  double** d_V = (double**)ptrs[pi++];
+  int* d_ldv = (int*)ptrs[pi++];
+  double* d_dwork = (double*)ptrs[pi++];
+  int* d_rkwork = (int*)ptrs[pi++];
+  int* d_active_count = (int*)ptrs[pi++];
+
+  hipStream_t s = batch_stream();
+  hipEvent_t ev;
+  ck(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event");
+  ck(hipEventRecord(ev, caller), "event");
+  ck(hipStreamWaitEvent(s, ev, 0), "wait event");
+
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    if (bytes) ck(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s), "H2D batch");
+  };
+  for (int g = 0; g < 2; g++) {
+    const GroupTables& T = grp[g];
+    up(dg[g].cols, T.cols.data(), T.cols.size() * sizeof(int));
+    up(dg[g].sg, T.sg.data(), T.sg.size());
+    up(dg[g].m, T.m.data(), T.m.size() * sizeof(int));
+    up(dg[g].nfirst, T.nfirst.data(), T.nfirst.size() * sizeof(int));
+    up(dg[g].slot_prob, T.slot_prob.data(), T.slot_prob.size() * sizeof(int));
+    up(dg[g].slot_k, T.slot_k.data(), T.slot_k.size() * sizeof(int));
+  }
+  std::vector<double*> gp(count), lp(count), vp(count);
+  std::vector<int> zeros(count, 0), ldg_v(count), n_v(count), ldv_v(count);
+  for (int i = 0; i < count; i++) {
+    gp[i] = (double*)G[i];
+    lp[i] = lambda[i];
+    vp[i] = (double*)V[i];
+    ldg_v[i] = ldg[i];
+    n_v[i] = n[i];
+    ldv_v[i] = ldv[i];
+  }
+  up(d_gptr, gp.data(), count * sizeof(double*));
+  up(d_ldg, ldg_v.data(), count * sizeof(int));
+  up(d_nrow, n_v.data(), count * sizeof(int));
+  up(d_width, width.data(), count * sizeof(int));
+  up(d_npairs, npairs.data(), count * sizeof(int));
+  up(d_nsteps, nsteps.data(), count * sizeof(int));
+  up(d_step, zeros.data(), count * sizeof(int));
+  up(d_sweep, zeros.data(), count * sizeof(int));
+  up(d_status, zeros.data(), count * sizeof(int));
+  up(d_tab_base, tab_base.data(), count * sizeof(int));
+  up(d_bad, zeros.data(), count * sizeof(int));
+  up(d_zero, zeros.data(), count * sizeof(int));
+  std::vector<SweepStats> st0(count);
+  std::memset(st0.data(), 0, count * sizeof(SweepStats));
+  up(d_st, st0.data(), count * sizeof(SweepStats));
+  std::vector<double> off0(count, 0.0);
+  up(d_final_off, off0.data(), count * sizeof(double));
+  up(d_cm_off, cm_off.data(), (count + 1) * sizeof(int));
+  up(d_colmap, colmap_all.data(), colmap_all.size() * sizeof(int));
+  up(d_sgn, sgn_all.data(), sgn_all.size());
+  up(d_lam, lp.data(), count * sizeof(double*));
+  up(d_V, vp.data(), count * sizeof(double*));
+  up(d_ldv, ldv_v.data(), count * sizeof(int));
+
+  // non-finite inputs are reported (status 3) and left out
+  launch_batch_check_finite(count, d_gptr, d_ldg, d_nrow, d_width, d_bad, s);
+  ck(hipGetLastError(), "launch");
+  std::vector<int> bad(count);
+  ck(hipMemcpyAsync(bad.data(), d_bad, count * sizeof(int), hipMemcpyDeviceToHost, s), "D2H");
+  ck(hipStreamSynchronize(s), "sync");
+  std::vector<int> active(count, 0), status(count, 0);
+  int nactive = 0;
+  for (int i = 0; i < count; i++) {
+    if (bad[i]) status[i] = JJ_NONFINITE;
+    active[i] = (!bad[i] && nsteps[i] > 0) ? 1 : 0;
+    nactive += active[i];
+  }
+  up(d_active, active.data(), count * sizeof(int));
+  up(d_status, status.data(), count * sizeof(int));
+  up(d_active_count, &nactive, sizeof(int));
+
+  // rotation threshold per problem: tol, or n * 2^-53 by default
+  std::vector<double> ptol(count);
+  for (int i = 0; i < count; i++) ptol[i] = tol > 0.0 ? tol : (double)n[i] * std::ldexp(1.0, -53);
+  up(d_tol, ptol.data(), count * sizeof(double));
+  const double btol = 0.0;  // unused: the pivot solver reads the per-problem value
+  const bool block_oriented = o.inner_mode == 0;
+  const int pmode = block_oriented ? 2 : 0;
+  const int imax = block_oriented ? 1 : (o.inner_max_sweeps > 0 ? o.inner_max_sweeps : 12);
+
+  Batch bt[2];
+  for (int g = 0; g < 2; g++) {
+    bt[g].slot_prob = dg[g].slot_prob;
+    bt[g].slot_k = dg[g].slot_k;
+    bt[g].tab_base = d_tab_base;
+    bt[g].npairs = d_npairs;
+    bt[g].step = d_step;
+    bt[g].active = d_active;
+    bt[g].gptr = d_gptr;
+    bt[g].ldg = d_ldg;
+    bt[g].nrow = d_nrow;
+    bt[g].st = d_st;
+    bt[g].tol = d_tol;
+  }
+  auto one_step = [&]() {
+    for (int g = 0; g < 2; g++) {
+      if (grp[g].slots == 0) continue;
+      PivotList pl{dg[g].cols, dg[g].sg, dg[g].m, dg[g].nfirst, grp[g].slots};
+      (g ? launch_gram_c128 : launch_gram_f64)(nullptr, 0, 0, pl, 1, rows_g[g], dg[g].part, s, bt[g]);
+    }
+    for (int g = 0; g < 2; g++) {
+      if (grp[g].slots == 0) continue;
+      PivotList pl{dg[g].cols, dg[g].sg, dg[g].m, dg[g].nfirst, grp[g].slots};
+      (g ? launch_pivot_c128 : launch_pivot_f64)(dg[g].part, 1, 0, rows_g[g], pl, btol, imax, pmode, 0, dg[g].W,
+                                                 dg[g].rot, nullptr, s, bt[g]);
+    }
+    for (int g = 0; g < 2; g++) {
+      if (grp[g].slots == 0) continue;
+      PivotList pl{dg[g].cols, dg[g].sg, dg[g].m, dg[g].nfirst, grp[g].slots};
+      (g ? launch_update_c128 : launch_update_f64)(nullptr, 0, 0, pl, dg[g].W, dg[g].rot, 256, s, bt[g], nch_u[g]);
+    }
+    launch_batch_advance(count, d_nsteps, d_step, d_sweep, d_active, d_status, d_st, d_final_off, max_sweeps,
+                         d_active_count, s);
+  };
+
+  // a round of steps captured once, replayed until no problem is active
+  int max_steps = 0;
+  for (int i = 0; i < count; i++) max_steps = std::max(max_steps, nsteps[i]);
+  const int kRound = 8;
+  const long long step_cap = (long long)max_sweeps * std::max(max_steps, 1) + kRound;
+  int left = nactive;
+  if (left > 0) {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ck(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+    for (int r = 0; r < kRound; r++) one_step();
+    ck(hipStreamEndCapture(s, &graph), "end capture");
+    ck(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "instantiate");
+    for (long long done = 0; left > 0 && done < step_cap; done += kRound) {
+      ck(hipGraphLaunch(exec, s), "graph launch");
+      ck(hipMemcpyAsync(&left, d_active_count, sizeof(int), hipMemcpyDeviceToHost, s), "D2H");
+      ck(hipStreamSynchronize(s), "sync");
+    }
+    hipGraphExecDestroy(exec);
+    hipGraphDestroy(graph);
+  }
+
+  launch_batch_finalize(count, d_gptr, d_ldg, d_nrow, d_width, d_colmap, d_cm_off, d_sgn, d_lam, d_V, d_ldv, d_dwork,
+                        d_rkwork, d_zero, s);
+  ck(hipGetLastError(), "launch");
+  std::vector<int> zero(count), sweeps(count);
+  std::vector<double> foff(count);
+  ck(hipMemcpyAsync(status.data(), d_status, count * sizeof(int), hipMemcpyDeviceToHost, s), "D2H");
+  ck(hipMemcpyAsync(active.data(), d_active, count * sizeof(int), hipMemcpyDeviceToHost, s), "D2H");
+  ck(hipMemcpyAsync(zero.data(), d_zero, count * sizeof(int), hipMemcpyDeviceToHost, s), "D2H");
+  ck(hipMemcpyAsync(sweeps.data(), d_sweep, count * sizeof(int), hipMemcpyDeviceToHost, s), "D2H");
+  ck(hipMemcpyAsync(foff.data(), d_final_off, count * sizeof(double), hipMemcpyDeviceToHost, s), "D2H");
+  ck(hipStreamSynchronize(s), "sync");
+  hipEventDestroy(ev);
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int worst = 0;
+  for (int i = 0; i < count; i++) {
+    int st = status[i];
+    if (active[i]) st = JJ_NOT_CONVERGED;  // step cap reached
+    if (st == JJ_OK && zero[i]) st = JJ_BREAKDOWN;
+    worst = std::max(worst, st);
+    if (info) {
+      std::memset(&info[i], 0, sizeof(jj_info));
+      info[i].status = st;
+      info[i].sweeps = sweeps[i];
+      info[i].block_width = plans[i].nbl >= 1 && plans[i].off.size() > 1 ? plans[i].off[1] - plans[i].off[0] : 0;
+      info[i].nblocks = plans[i].nbl;
+      info[i].final_offdiag = foff[i];
+      info[i].seconds = secs;
+    }
+  }
+  return worst;
 }
 
 static int check_args(int dtype, const void* G, const signed char* J, int n, int ldg, const double* lambda,
@@ -579,13 +969,17 @@ int jjacobi_solve_batched(int count, const int* dtype, void* const* G, const sig
     int a = check_args(dtype[k], G[k], J[k], n[k], ldg[k], lambda[k], V[k], ldv[k]);
     if (a < 0) return a;
   }
-  int worst = 0;
-  for (int k = 0; k < count; k++) {
-    int s = jjacobi_solve_ex(dtype[k], G[k], J[k], n[k], ldg[k], lambda[k], V[k], ldv[k], tol, max_sweeps, opts,
-                             info ? info + k : nullptr);
-    worst = std::max(worst, s);
+  jj_opts o;
+  jjacobi_default_opts(&o);
+  if (opts) o = *opts;
+  std::lock_guard<std::mutex> lk(g_mutex);
+  try {
+    return solve_batch(count, dtype, G, J, n, ldg, lambda, V, ldv, tol, max_sweeps, o, info);
+  } catch (const HipFail&) {
+    if (info)
+      for (int k = 0; k < count; k++) info[k].status = JJ_HIP_ERROR;
+    return JJ_HIP_ERROR;
   }
-  return worst;
 }
 
 const char* jjacobi_status_string(int status) {

@@ -1,0 +1,94 @@
+"""Batched solves (jjacobi_solve_batched through the C ABI): every problem of a
+mixed batch against the CPU oracle, status paths inside a batch, and
+determinism of the graph-replayed step loop."""
+import numpy as np
+import pytest
+
+import jjgen
+import oracle
+from _pins import EPS, kappa_s, rel_err
+from test_gpu_parity import check_parity, check_vectors
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def batched(Gs, Js, **kw):
+    import paper_1008_4166_amd as jj
+    ts = [torch.from_numpy(np.ascontiguousarray(G)).cuda() for G in Gs]
+    lams, Vs, infos, worst = jj.solve_batched(ts, Js, **kw)
+    torch.cuda.synchronize()
+    return [l.cpu().numpy() for l in lams], [V.cpu().numpy() for V in Vs], infos, worst
+
+
+def _mixed_batch(seed=0):
+    sizes = [2, 5, 16, 33, 64, 65, 100, 130, 200, 97, 40, 150]
+    Gs, Js = [], []
+    for k, n in enumerate(sizes):
+        cplx = k % 2 == 1
+        G, J, _ = jjgen.make(n, cplx, (k * 7 + n // 3) % (n + 1), 1e-5, 1e2, seed=900 + seed * 100 + k)
+        Gs.append(G)
+        Js.append(J)
+    return Gs, Js
+
+
+@pytest.mark.parametrize("variant", [dict(), dict(block_width=16), dict(inner_mode=1)])
+def test_mixed_batch_matches_oracle(variant):
+    Gs, Js = _mixed_batch()
+    lams, Vs, infos, worst = batched(Gs, Js, **variant)
+    assert worst == 0, [i["status"] for i in infos]
+    for G, J, lam, V, info in zip(Gs, Js, lams, Vs, infos):
+        assert info["status"] == 0
+        check_parity(G, J, lam, "batched n=%d" % G.shape[0])
+        check_vectors(G, J, lam, V)
+
+
+def test_batch_status_paths_and_tiny():
+    Gs, Js = _mixed_batch(seed=1)
+    Gbad = Gs[3].copy()
+    Gbad[1, 2] = np.nan
+    Gs.append(Gbad)
+    Js.append(Js[3])
+    Gs.append(np.array([[-2.0]]))
+    Js.append(np.array([-1], dtype=np.int8))
+    lams, Vs, infos, worst = batched(Gs, Js)
+    assert infos[-2]["status"] == 3
+    assert infos[-1]["status"] == 0 and lams[-1][0] == -4.0
+    assert worst == 3
+    for G, J, lam, info in zip(Gs[:-2], Js[:-2], lams[:-2], infos[:-2]):
+        assert info["status"] == 0
+        check_parity(G, J, lam)
+
+
+def test_batch_sweep_cap():
+    Gs, Js = _mixed_batch(seed=2)
+    lams, Vs, infos, worst = batched(Gs, Js, max_sweeps=1)
+    assert worst == 1
+    assert any(i["status"] == 1 for i in infos)
+
+
+def test_batch_deterministic_and_equal_to_replays():
+    Gs, Js = _mixed_batch(seed=3)
+    a, Va, _, _ = batched(Gs, Js)
+    b, Vb, _, _ = batched(Gs, Js)
+    for x, y, u, v in zip(a, b, Va, Vb):
+        assert np.array_equal(x, y) and np.array_equal(u, v)
+
+
+def test_batch_of_workload_sizes():
+    # a small sample of the mixed-size workload (n in [16, 512], half complex)
+    specs = jjgen.batch_recipe(count=16)
+    Gs, Js = [], []
+    for sp in specs:
+        G, J, _ = jjgen.batch_member(sp)
+        Gs.append(G)
+        Js.append(J)
+    lams, Vs, infos, worst = batched(Gs, Js)
+    assert worst == 0
+    for G, J, lam, info in zip(Gs, Js, lams, infos):
+        if G.shape[0] <= 200:
+            check_parity(G, J, lam)
+        # inertia and trace invariants for all sizes
+        assert np.sum(lam > 0) == np.sum(J > 0)
+        tr = np.sum(J.astype(float) * np.sum(np.abs(G) ** 2, axis=0))
+        assert abs(np.sum(lam) - tr) <= 64 * G.shape[0] * EPS * np.sum(np.abs(lam))
