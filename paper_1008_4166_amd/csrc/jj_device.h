@@ -78,6 +78,33 @@ __device__ __forceinline__ bool batch_resolve(const Batch& b, int slot, int& pid
   return true;
 }
 
+// Workgroups of a (chunks x slots) grid placed by XCD.  The dispatcher hands
+// linear workgroup L to XCD L % 8; the pairs (slot, chunk), ordered by
+// (slot % 8, slot / 8, chunk), are cut into consecutive runs, one per XCD, so
+// that all chunks of slot s run on XCD s % 8 whenever the counts allow it (always
+// when the number of slots is a multiple of 8), the same XCD as the pivot
+// workgroup of slot s (a one-dimensional grid over slots).  The partials the
+// pivot reads and the W_P the update reads then stay in that XCD's L2.
+__device__ __forceinline__ void xcd_slot_chunk(int& slot, int& ch) {
+  const int nch = gridDim.x, count = gridDim.y;
+  const int T = nch * count;
+  const int L = blockIdx.x + nch * blockIdx.y;
+  const int x = L & 7;
+  int pos = L >> 3;
+  for (int y = 0; y < x; y++) pos += (T - y + 7) >> 3;  // workgroups on the XCDs before x
+  for (int r = 0; r < 8; r++) {
+    const int run = ((count - r + 7) >> 3) * nch;  // pairs whose slot is r mod 8
+    if (pos < run) {
+      slot = r + 8 * (pos / nch);
+      ch = pos % nch;
+      return;
+    }
+    pos -= run;
+  }
+  slot = 0;
+  ch = 0;  // not reached: the runs cover all T pairs
+}
+
 // ---- launchers (all asynchronous on `stream`) ----
 
 // part[p][ch][r*64 + c] = sum over rows of chunk ch of conj(G[row, col(r)]) G[row, col(c)],

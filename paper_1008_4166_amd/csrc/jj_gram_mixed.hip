@@ -29,7 +29,9 @@ __global__ __launch_bounds__(256) void k_gram_f32mix(const double* __restrict__ 
                                                      const int* __restrict__ cols, const int* __restrict__ mlist,
                                                      int rows_per_chunk, double* __restrict__ part, Batch bt) {
   __shared__ d4m red[10][64];
-  const int slot = blockIdx.y, ch = blockIdx.x, nch = gridDim.x;
+  const int nch = gridDim.x;
+  int slot, ch;
+  xcd_slot_chunk(slot, ch);
   int p = slot, ldg = ldg0, n = n0;
   double* Gm = const_cast<double*>(G0);
   SweepStats* stp = nullptr;
@@ -120,7 +122,9 @@ __global__ __launch_bounds__(256) void k_gram_c64mix(const double* __restrict__ 
                                                      const int* __restrict__ cols, const int* __restrict__ mlist,
                                                      int rows_per_chunk, double* __restrict__ part, Batch bt) {
   __shared__ d4m red[10][2][64];
-  const int slot = blockIdx.y, ch = blockIdx.x, nch = gridDim.x;
+  const int nch = gridDim.x;
+  int slot, ch;
+  xcd_slot_chunk(slot, ch);
   int p = slot, ldg = ldg0, n = n0;
   double* Gm = const_cast<double*>(G0);
   SweepStats* stp = nullptr;

@@ -37,7 +37,9 @@ __global__ __launch_bounds__(256) void k_gram_f64(const double* __restrict__ G0,
                                                   const int* __restrict__ cols, const int* __restrict__ mlist,
                                                   int rows_per_chunk, double* __restrict__ part, Batch bt) {
   __shared__ d4 red[2][10][64];
-  const int slot = blockIdx.y, ch = blockIdx.x, nch = gridDim.x;
+  const int nch = gridDim.x;
+  int slot, ch;
+  xcd_slot_chunk(slot, ch);
   int p = slot, ldg = ldg0, n = n0;
   double* Gm = const_cast<double*>(G0);
   SweepStats* stp = nullptr;
@@ -138,7 +140,8 @@ __global__ __launch_bounds__(256) void k_update_f64(double* __restrict__ G0, int
                                                     const int* __restrict__ cols, const int* __restrict__ mlist,
                                                     const double* __restrict__ Wg, const int* __restrict__ rotflag,
                                                     int rows_per_chunk, Batch bt) {
-  const int slot = blockIdx.y, ch = blockIdx.x;
+  int slot, ch;
+  xcd_slot_chunk(slot, ch);
   int p = slot, ldg = ldg0, n = n0;
   double* G = G0;
   SweepStats* stp = nullptr;
@@ -207,7 +210,9 @@ __global__ __launch_bounds__(256) void k_gram_c128(const double* __restrict__ G0
                                                    const int* __restrict__ cols, const int* __restrict__ mlist,
                                                    int rows_per_chunk, double* __restrict__ part, Batch bt) {
   __shared__ d4 red[10][2][64];
-  const int slot = blockIdx.y, ch = blockIdx.x, nch = gridDim.x;
+  const int nch = gridDim.x;
+  int slot, ch;
+  xcd_slot_chunk(slot, ch);
   int p = slot, ldg = ldg0, n = n0;
   double* Gm = const_cast<double*>(G0);
   SweepStats* stp = nullptr;
@@ -300,7 +305,8 @@ __global__ __launch_bounds__(256) void k_update_c128(double* __restrict__ G0, in
                                                      const int* __restrict__ cols, const int* __restrict__ mlist,
                                                      const double* __restrict__ Wg, const int* __restrict__ rotflag,
                                                      int rows_per_chunk, Batch bt) {
-  const int slot = blockIdx.y, ch = blockIdx.x;
+  int slot, ch;
+  xcd_slot_chunk(slot, ch);
   int p = slot, ldg = ldg0, n = n0;
   double* G = G0;
   SweepStats* stp = nullptr;

@@ -62,8 +62,6 @@ __device__ __forceinline__ double conj_of(double a) { return a; }
 __device__ __forceinline__ double2 conj_of(double2 a) { return double2{a.x, -a.y}; }
 __device__ __forceinline__ double real_of(double a) { return a; }
 __device__ __forceinline__ double real_of(double2 a) { return a.x; }
-__device__ __forceinline__ double abs_of(double a) { return fabs(a); }
-__device__ __forceinline__ double abs_of(double2 a) { return hypot(a.x, a.y); }
 __device__ __forceinline__ bool finite_of(double a) { return isfinite(a); }
 __device__ __forceinline__ bool finite_of(double2 a) { return isfinite(a.x) && isfinite(a.y); }
 
@@ -89,27 +87,49 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Reciprocal and reciprocal square root from the hardware estimates (about
+// 2^-23 relative) refined by two Newton steps each, r <- r + r (1 - x r) and
+// y <- y + (y/2)(1 - x y^2), which leaves an error of about one unit in the last
+// place with no preferred direction.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+#pragma unroll
+  for (int it = 0; it < 2; it++) r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+__device__ __forceinline__ double rsqrt_nr(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+  for (int it = 0; it < 2; it++) y = fma(0.5 * y, fma(-(d * y), y, 1.0), y);
+  return y;
+}
+// sqrt(x) for x >= 0 (exact zero for zero), without a branch
+__device__ __forceinline__ double sqrt_nr(double x) {
+  const double y = x * rsqrt_nr(fmax(x, 1e-300));
+  return x > 0.0 ? y : 0.0;
+}
+
 // Rotation for the 2x2 pivot [arr eta; eta ass] (eta real) with sigma = +j_r j_s
 // (Algorithm 3.1 read with sigma = +j_r j_s).  With N = sigma a_ss - a_rr
 // (= 2 eta theta), t = sgn(theta) / (|theta| + sqrt(theta^2 + sigma)) is
 // evaluated as sgn(N eta) 2|eta| / (|N| + sqrt(N^2 + 4 sigma eta^2)) after an
 // exact power-of-two scaling of N and eta; cs = 1/sqrt(1 + sigma t^2), with
-// 1 - t^2 = (1-|t|)(1+|t|).  The hyperbolic rotation exists iff |N| > 2|eta|.
+// 1 - t^2 = (1-|t|)(1+|t|), and sn = cs t, so that the applied rotation is
+// J-unitary to working precision whatever the rounding of t.  The hyperbolic
+// rotation exists iff |N| > 2|eta|.
 // Returns 0: below tol, 1: (cs, sn) set, -1: hyperbolic breakdown.
 __device__ __forceinline__ int rot_params(double arr, double ass, double eta, double sigma, double tol,
                                           double* cs, double* sn) {
-  if (!(fabs(eta) > tol * sqrt(arr) * sqrt(ass))) return 0;
+  if (!(fabs(eta) > tol * (sqrt_nr(arr) * sqrt_nr(ass)))) return 0;
   const double N = sigma * ass - arr;
   const double e2 = 2.0 * fabs(eta);
   if (sigma < 0.0 && fabs(N) <= e2) return -1;
   const int ex = ilogb(fmax(fabs(N), e2));
   const double Ns = ldexp(N, -ex), Es = ldexp(e2, -ex);
-  double t = Es / (fabs(Ns) + sqrt(Ns * Ns + sigma * (Es * Es)));
+  double t = Es * rcp_nr(fabs(Ns) + sqrt_nr(fma(Ns, Ns, sigma * (Es * Es))));
   if ((N < 0.0) != (eta < 0.0)) t = -t;
   const double at = fabs(t);
-  // correctly rounded sqrt and division: a biased reciprocal square root would
-  // make every rotation slightly non-J-unitary in the same direction
-  const double c = 1.0 / sqrt(sigma > 0.0 ? 1.0 + t * t : (1.0 - at) * (1.0 + at));
+  const double c = rsqrt_nr(sigma > 0.0 ? fma(t, t, 1.0) : (1.0 - at) * (1.0 + at));
   *cs = c;
   *sn = c * t;
   return 1;
@@ -118,9 +138,22 @@ __device__ __forceinline__ int rot_params(double arr, double ass, double eta, do
 // Move a double across lanes with a DPP pattern (both 32-bit halves).
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
+}
+
+// Lane exchanges within a wavefront: DPP row rotation by 8 inside 16-lane rows
+// (the value of lane ^ 8), and a lane permute from a byte address (lane ^ x) * 4.
+__device__ __forceinline__ double xor8_of(double v) { return dpp_f64<0x128>(v); }
+__device__ __forceinline__ double2 xor8_of(double2 v) { return double2{xor8_of(v.x), xor8_of(v.y)}; }
+__device__ __forceinline__ double bperm_of(double v, int addr) {
+  const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(v));
+  const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double2 bperm_of(double2 v, int addr) {
+  return double2{bperm_of(v.x, addr), bperm_of(v.y, addr)};
 }
 
 // Sum over the LPS lanes of a slot (slots are aligned groups of LPS lanes).
@@ -147,20 +180,119 @@ __device__ __forceinline__ int pair_rotation(double arr, double ass, double are,
                                              double tol, double* cs, double* sn, double* pr, double* pi) {
   double eta;
   if (cplx) {
-    const double aabs = hypot(are, aim);
-    eta = (are < 0.0 ? -1.0 : 1.0) * aabs;
+    // |a_rs| with an exact power-of-two scaling against under/overflow
+    const int ex = ilogb(fmax(fmax(fabs(are), fabs(aim)), 1e-300));
+    const double xr = ldexp(are, -ex), xi = ldexp(aim, -ex);
+    const double ms = sqrt_nr(fma(xr, xr, xi * xi));
+    const double einv = (are < 0.0 ? -1.0 : 1.0) * rcp_nr(ms);
+    eta = (are < 0.0 ? -1.0 : 1.0) * ldexp(ms, ex);
+    *pr = xr * einv;
+    *pi = xi * einv;
   } else {
     eta = are;
   }
-  int rc = rot_params(arr, ass, eta, sigma, tol, cs, sn);
-  if (rc > 0 && cplx) {
-    *pr = are / eta;
-    *pi = aim / eta;
-  } else {
+  const int rc = rot_params(arr, ass, eta, sigma, tol, cs, sn);
+  if (!(rc > 0 && cplx)) {
     *pr = 1.0;
     *pi = 0.0;
   }
   return rc;
+}
+
+// Value of v in lane l (l uniform across the wave).
+__device__ __forceinline__ double readlane_of(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double2 readlane_of(double2 v, int l) {
+  return double2{readlane_of(v.x, l), readlane_of(v.y, l)};
+}
+
+// |a| f for a scale factor f > 0 (the scaled off-diagonal measure)
+__device__ __forceinline__ double abs_scaled(double a, double f) { return fabs(a) * f; }
+__device__ __forceinline__ double abs_scaled(double2 a, double f) {
+  const double x = a.x * f, y = a.y * f;
+  return sqrt_nr(fma(x, x, y * y));
+}
+
+// One Cholesky panel (rows r0..r0+kn-1) held as s[ii] = S[r0 + ii][lane]:
+// row k of R is row k of S times 1/sqrt(s_kk), then each later row i of the
+// panel subtracts conj(r_ki) * (row k of R), r_ki being lane i's entry.  Returns
+// nonzero if a pivot s_kk is not positive and finite (the caller stops after
+// the panel; the steps after it run on meaningless values).
+template <bool FULL, typename T>
+__device__ __forceinline__ int chol_panel(T (&s)[16], int r0, int kn, int lane) {
+  int bad = 0;
+#pragma unroll
+  for (int kk = 0; kk < 16; kk++) {
+    if (FULL || kk < kn) {
+      const double d = real_of(readlane_of(s[kk], r0 + kk));  // uniform across the wave
+      bad |= !(d > 0.0 && isfinite(d));
+      const double y = rsqrt_nr(d);
+      s[kk] = scale(s[kk], y);
+      if (lane == r0 + kk) s[kk] = scale(one_like(s[kk]), d * y);  // real positive diagonal
+#pragma unroll
+      for (int ii = kk + 1; ii < 16; ii++) {
+        if (FULL || ii < kn) {
+          const T rki = readlane_of(s[kk], r0 + ii);
+          s[ii] = lin2(1.0, s[ii], -1.0, cmul_conj_first(conj_of(rki), s[kk]));
+        }
+      }
+    }
+  }
+  return bad;
+}
+
+typedef double d4p __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ d4p mfma16p(double a, double b, d4p c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Trailing update of the Cholesky after the panel of rows r0..r0+15 (one
+// wavefront): S[16I.., 16J..] -= R_p[:, 16I..]^* R_p[:, 16J..] for the tiles
+// r0 + 16 <= 16I <= 16J < m.  MFMA lane l supplies A[l%16][l/16], B[l/16][l%16]
+// and holds D[4v + l/16][l%16]; S and R share the column-major LDS array.
+__device__ __forceinline__ void chol_trailing(double* R, int r0, int m, int lane) {
+  const int c16 = lane & 15, g = lane >> 4;
+  const int tn = (m + 15) >> 4;
+  for (int I = (r0 >> 4) + 1; I < tn; I++)
+    for (int J = I; J < tn; J++) {
+      d4p acc;
+#pragma unroll
+      for (int v = 0; v < 4; v++) acc[v] = R[(16 * J + c16) * LDR + 16 * I + 4 * v + g];
+#pragma unroll
+      for (int q = 0; q < 4; q++)
+        acc = mfma16p(-R[(16 * I + c16) * LDR + r0 + 4 * q + g], R[(16 * J + c16) * LDR + r0 + 4 * q + g], acc);
+#pragma unroll
+      for (int v = 0; v < 4; v++) R[(16 * J + c16) * LDR + 16 * I + 4 * v + g] = acc[v];
+    }
+}
+// Complex: Re -= Xr^T Yr + Xi^T Yi, Im -= Xr^T Yi - Xi^T Yr.
+__device__ __forceinline__ void chol_trailing(double2* R, int r0, int m, int lane) {
+  const int c16 = lane & 15, g = lane >> 4;
+  const int tn = (m + 15) >> 4;
+  for (int I = (r0 >> 4) + 1; I < tn; I++)
+    for (int J = I; J < tn; J++) {
+      d4p are, aim;
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const double2 a = R[(16 * J + c16) * LDR + 16 * I + 4 * v + g];
+        are[v] = a.x;
+        aim[v] = a.y;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const double2 x = R[(16 * I + c16) * LDR + r0 + 4 * q + g];
+        const double2 y = R[(16 * J + c16) * LDR + r0 + 4 * q + g];
+        are = mfma16p(-x.x, y.x, are);
+        are = mfma16p(-x.y, y.y, are);
+        aim = mfma16p(-x.x, y.y, aim);
+        aim = mfma16p(x.y, y.x, aim);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; v++) R[(16 * J + c16) * LDR + 16 * I + 4 * v + g] = double2{are[v], aim[v]};
+    }
 }
 
 template <bool CPLX, int LPS>
@@ -174,8 +306,8 @@ __global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ p
   constexpr int NT = 32 * LPS;
   constexpr int RPL = kMaxPivot / LPS;  // rows of one column held by a lane
   __shared__ T lds[2 * kMaxPivot * LDR];
-  __shared__ double redv[NT];
-  __shared__ __align__(16) T rowb[kMaxPivot];
+  __shared__ double redv[NT / 64];
+  __shared__ double s_dinv[kMaxPivot];
   __shared__ int s_cnt, s_bad;
   __shared__ signed char s_sg[kMaxPivot];
   __shared__ int ring_sg[2][32];
@@ -199,19 +331,37 @@ __global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ p
   const signed char* sg = s_sg;  // signs of the pivot's columns, in LDS
 
   // ---- 1. A_P = sum of the chunk partials (upper 16x16 tiles), Hermitian fill ----
-  // all chunk loads of an element are issued before the (fixed-order) sum
+  // Thread u of each 256-element tile takes element (u / 16, u % 16) of it; the
+  // chunk loads of EB tiles are issued together, then summed in chunk order.
   const T* P = reinterpret_cast<const T*>(part) + (size_t)bslot * nch * (kMaxPivot * kMaxPivot);
-  for (int e = tid; e < kMaxPivot * kMaxPivot; e += NT) {
-    int r = e >> 6, c = e & 63;
-    if (r < m && c < m && (r >> 4) <= (c >> 4)) {
-      T v[kMaxChunks];
+  {
+    constexpr int EB = CPLX ? 2 : 4;
+    for (int u0 = tid; u0 < 10 * 256; u0 += EB * NT) {
+      T v[EB][kMaxChunks];
+      int rr[EB], cc[EB];
 #pragma unroll
-      for (int k = 0; k < kMaxChunks; k++)
-        v[k] = k < nchp ? P[(size_t)k * (kMaxPivot * kMaxPivot) + e] : zero_of(T());
-      T s = v[0];
+      for (int h = 0; h < EB; h++) {
+        const int u = u0 + h * NT, t = u >> 8, w = u & 255;
+        // upper tiles in the order (0,0) (0,1) (0,2) (0,3) (1,1) (1,2) (1,3) (2,2) (2,3) (3,3)
+        const int I = t < 4 ? 0 : (t < 7 ? 1 : (t < 9 ? 2 : 3));
+        const int J = t - (I == 0 ? 0 : (I == 1 ? 3 : (I == 2 ? 5 : 6)));
+        const int r = 16 * I + (w >> 4), c = 16 * J + (w & 15);
+        const bool ok = t < 10 && r < m && c < m;
+        rr[h] = ok ? r : -1;
+        cc[h] = c;
 #pragma unroll
-      for (int k = 1; k < kMaxChunks; k++) s = lin2(1.0, s, 1.0, v[k]);
-      R[c * LDR + r] = s;
+        for (int k = 0; k < kMaxChunks; k++)
+          v[h][k] = (ok && k < nchp) ? P[(size_t)k * (kMaxPivot * kMaxPivot) + r * kMaxPivot + c] : zero_of(T());
+      }
+#pragma unroll
+      for (int h = 0; h < EB; h++) {
+        if (rr[h] >= 0) {
+          T sum = v[h][0];
+#pragma unroll
+          for (int k = 1; k < kMaxChunks; k++) sum = lin2(1.0, sum, 1.0, v[h][k]);
+          R[cc[h] * LDR + rr[h]] = sum;
+        }
+      }
     }
   }
   if (tid == 0) {
@@ -226,25 +376,24 @@ __global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ p
   __syncthreads();
 
   // ---- 2. scaled off-diagonal test; zero or non-finite diagonal = breakdown ----
+  if (tid < kMaxPivot) {
+    const double d = tid < m ? real_of(R[tid * LDR + tid]) : 1.0;
+    const bool okd = d > 0.0 && isfinite(d);
+    if (!okd) atomicOr(&s_bad, 1);
+    s_dinv[tid] = okd ? rsqrt_nr(d) : 0.0;
+  }
+  __syncthreads();
   double off = 0.0;
   for (int e = tid; e < kMaxPivot * kMaxPivot; e += NT) {
-    int r = e >> 6, c = e & 63;
-    if (r < m && c < m && r < c) {
-      double v = abs_of(R[c * LDR + r]) / (sqrt(real_of(R[r * LDR + r])) * sqrt(real_of(R[c * LDR + c])));
-      off = fmax(off, v);
-    }
+    const int r = e & 63, c = e >> 6;
+    if (r < c && c < m) off = fmax(off, abs_scaled(R[c * LDR + r], s_dinv[r] * s_dinv[c]));
   }
-  for (int k = tid; k < m; k += NT) {
-    double d = real_of(R[k * LDR + k]);
-    if (!(d > 0.0) || !isfinite(d)) atomicOr(&s_bad, 1);
-  }
-  redv[tid] = off;
+#pragma unroll
+  for (int msk = 32; msk > 0; msk >>= 1) off = fmax(off, __shfl_xor(off, msk));
+  if ((tid & 63) == 0) redv[tid >> 6] = off;
   __syncthreads();
-  for (int s = NT / 2; s > 0; s >>= 1) {
-    if (tid < s) redv[tid] = fmax(redv[tid], redv[tid + s]);
-    __syncthreads();
-  }
   off = redv[0];
+  for (int w = 1; w < NT / 64; w++) off = fmax(off, redv[w]);
   if (tid == 0) atomic_max_nonneg(&st->max_off_bits, isfinite(off) ? off : 1.0e300);
   if (s_bad || off <= tol) {
     if (tid == 0) {
@@ -254,62 +403,32 @@ __global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ p
     return;
   }
 
-  // ---- 3. Cholesky A_P = R^* R by one wavefront, without workgroup barriers ----
-  // Lane i keeps row i of the Schur complement in registers.  Phase k: lane k
-  // publishes its (final) row k to LDS, every lane i > k subtracts
-  // (conj(a_ki)/a_kk) * row k from its row; lanes i <= k are finished.  Row i of
-  // R is row i of the last Schur complement scaled by 1/sqrt(a_ii); the entries
-  // left of the diagonal are cleared.
+  // ---- 3. Cholesky A_P = R^* R by wavefront 0, in panels of 16 rows ----
+  // Panel rows r0..r0+15: lane j holds S[r0 + ii][j] of the current Schur
+  // complement S in registers.  Row k of R is row k of S times 1/sqrt(s_kk);
+  // the later rows i of the panel then subtract conj(r_ki) * (row k of R), with
+  // r_ki read from lane i.  The rows below the panel take the same update as
+  // 16x16 tiles on the FP64 matrix cores (S_IJ -= R_pI^* R_pJ), through LDS.
   {
-    T* rowbuf = reinterpret_cast<T*>(rowb);
     int bad = 0;
     if (tid < 64) {
-      const int i = tid;
-      T a[kMaxPivot];
+      const int lane = tid;
+      for (int r0 = 0; r0 < m; r0 += 16) {
+        const int kn = min(16, m - r0);
+        T s[16];
 #pragma unroll
-      for (int c = 0; c < kMaxPivot; c++) a[c] = (i < m && c < m) ? R[c * LDR + i] : zero_of(T());
-      double mydiag = 1.0;
-      for (int k = 0; k < m; k++) {
-        if (i == k) {  // publish the part of row k right of column k (16-column groups)
+        for (int ii = 0; ii < 16; ii++)
+          s[ii] = (lane >= r0 && lane < m && ii < kn) ? R[lane * LDR + r0 + ii] : zero_of(T());
+        bad = kn == 16 ? chol_panel<true>(s, r0, kn, lane) : chol_panel<false>(s, r0, kn, lane);
+        if (bad) break;
+        // rows r0..r0+kn-1 of R, zero left of the diagonal and beyond column m
 #pragma unroll
-          for (int g = 0; g < kMaxPivot / 16; g++)
-            if (16 * g + 15 >= k) {
-#pragma unroll
-              for (int c = 0; c < 16; c++) rowbuf[16 * g + c] = a[16 * g + c];
-            }
-        }
-        wave_sync();
-        const double d = real_of(rowbuf[k]);
-        if (!(d > 0.0) || !isfinite(d)) {
-          bad = 1;
-          break;
-        }
-        if (i == k) mydiag = d;
-        const double dinv = 1.0 / d;
-        // S_ic -= S_ik S_kc / S_kk with S_ik = conj(S_ki) = conj(rowbuf[i]); columns
-        // c <= k of the rows i > k are left of the diagonal and never read again
-        T f = (i > k && i < m) ? scale(conj_of(rowbuf[i]), dinv) : zero_of(T());
-#pragma unroll
-        for (int g = 0; g < kMaxPivot / 16; g++) {
-          if (16 * g + 15 > k) {
-            T rb[16];
-#pragma unroll
-            for (int c = 0; c < 16; c++) rb[c] = rowbuf[16 * g + c];
-#pragma unroll
-            for (int c = 0; c < 16; c++) a[16 * g + c] = lin2(1.0, a[16 * g + c], -1.0, cmul_conj_first(f, rb[c]));
-          }
-        }
-        wave_sync();
-      }
-      if (!bad) {
-        const double rs = 1.0 / sqrt(mydiag);
-#pragma unroll
-        for (int c = 0; c < kMaxPivot; c++) {
-          if (i < m && c < m) {
-            T v = (c < i) ? zero_of(T()) : scale(a[c], rs);
-            if (c == i) v = scale(one_like(v), sqrt(mydiag));  // real positive diagonal
-            R[c * LDR + i] = v;
-          }
+        for (int ii = 0; ii < 16; ii++)
+          if (ii < kn) R[lane * LDR + r0 + ii] = (lane < r0 + ii || lane >= m) ? zero_of(T()) : s[ii];
+        if (r0 + 16 < m) {
+          wave_sync();
+          chol_trailing(R, r0, m, lane);
+          wave_sync();
         }
       }
       if (tid == 0) s_bad = bad;
@@ -391,8 +510,15 @@ __global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ p
         __syncthreads();
       }
     }
-    // (b) cross pairs: first-block column `slot` stays in registers, second-block
-    // columns move one slot down per round through an LDS ring (aliasing R/W)
+    // (b) cross pairs: first-block column `slot` stays in registers while the
+    // second-block columns move between slots.  Two equal power-of-two blocks
+    // use the XOR schedule: in round q slot k meets second-block column
+    // k ^ gray(q); from one round to the next a single bit b of gray(q) flips, so
+    // every held column moves to slot k ^ 2^b, within the wavefront (DPP or lane
+    // permute) while that slot lies in the same wavefront and through LDS with a
+    // workgroup barrier otherwise (3 of 31 moves for 32 columns).  Other shapes
+    // use the ring: slot k meets column (k + q) mod L, all columns moving one
+    // slot down per round through LDS.
     if (L > 0 && n2 > 0) {
       T rr[RPL], wr[RPL], rs[RPL], ws[RPL];
       const bool have_r = slot < n1;
@@ -410,87 +536,121 @@ __global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ p
       T* ring1 = lds + 2 * 32 * kMaxPivot;  // each ring: 2 x 32 slots x 64 rows of T
       const double sr = have_r ? (double)sg[slot] : 0.0;
       double ss = slot < n2 ? (double)sg[n1 + slot] : 0.0;  // sign of the held second-block column
-      for (int q = 0; q < L; q++) {
-        int sidx = slot + q;  // second-block column held by this slot: (slot + q) mod L
-        if (sidx >= L) sidx -= L;
-        if (slot < L && have_r && sidx < n2) {
-          double arr = 0.0, ass = 0.0, are = 0.0, aim = 0.0;
+      // rotate the held pair (first-block column `slot`, held second-block column)
+      auto rotate_held = [&]() {
+        double arr = 0.0, ass = 0.0, are = 0.0, aim = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPL; i++) {
+          arr += abs2(rr[i]);
+          ass += abs2(rs[i]);
+          cdot(rr[i], rs[i], are, aim);
+        }
+        arr = slot_sum<LPS>(arr);
+        ass = slot_sum<LPS>(ass);
+        are = slot_sum<LPS>(are);
+        if (CPLX) aim = slot_sum<LPS>(aim);
+        const double sigma = sr * ss;
+        double cs, sn, pr, pi;
+        const int rc = pair_rotation(arr, ass, are, aim, CPLX, sigma, tol, &cs, &sn, &pr, &pi);
+        if (rc > 0) {
 #pragma unroll
           for (int i = 0; i < RPL; i++) {
-            arr += abs2(rr[i]);
-            ass += abs2(rs[i]);
-            cdot(rr[i], rs[i], are, aim);
+            T f = phase_mul(pr, pi, rr[i]), g = rs[i];
+            rr[i] = lin2(cs, f, -sigma * sn, g);
+            rs[i] = lin2(sn, f, cs, g);
+            T u = phase_mul(pr, pi, wr[i]), w = ws[i];
+            wr[i] = lin2(cs, u, -sigma * sn, w);
+            ws[i] = lin2(sn, u, cs, w);
           }
-          arr = slot_sum<LPS>(arr);
-          ass = slot_sum<LPS>(ass);
-          are = slot_sum<LPS>(are);
-          if (CPLX) aim = slot_sum<LPS>(aim);
-          const double sigma = sr * ss;
-          double cs, sn, pr, pi;
-          int rc = pair_rotation(arr, ass, are, aim, CPLX, sigma, tol, &cs, &sn, &pr, &pi);
-          if (rc > 0) {
+          cnt += (sub == 0);
+        } else if (rc < 0 && sub == 0) {
+          atomicOr(&s_bad, 1);
+        }
+      };
+      // publish the held column of every slot in `ring` (16-byte elements: two
+      // reals or one complex, so each lane moves its share with 128-bit LDS
+      // accesses) and take over the one of slot `from`, around a barrier
+      auto exchange_lds = [&](T* ringT, int* rsg, int from) {
+        double2* ring = reinterpret_cast<double2*>(ringT);
+        if (sub == 0) rsg[slot] = (int)ss;
+        if constexpr (CPLX) {
 #pragma unroll
-            for (int i = 0; i < RPL; i++) {
-              T f = phase_mul(pr, pi, rr[i]), g = rs[i];
-              rr[i] = lin2(cs, f, -sigma * sn, g);
-              rs[i] = lin2(sn, f, cs, g);
-              T u = phase_mul(pr, pi, wr[i]), w = ws[i];
-              wr[i] = lin2(cs, u, -sigma * sn, w);
-              ws[i] = lin2(sn, u, cs, w);
-            }
-            cnt += (sub == 0);
-          } else if (rc < 0 && sub == 0) {
-            atomicOr(&s_bad, 1);
+          for (int j = 0; j < RPL; j++) {
+            ring[(j * 32 + slot) * LPS + sub] = rs[j];
+            ring[((RPL + j) * 32 + slot) * LPS + sub] = ws[j];
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < RPL / 2; j++) {
+            ring[(j * 32 + slot) * LPS + sub] = double2{rs[2 * j], rs[2 * j + 1]};
+            ring[((RPL / 2 + j) * 32 + slot) * LPS + sub] = double2{ws[2 * j], ws[2 * j + 1]};
           }
         }
-        if (q + 1 < L) {
-          // slot k receives the second-block column of slot (k + 1) mod L; the
-          // ring holds 16-byte elements (two reals or one complex) so that each
-          // lane moves its share with 128-bit LDS accesses
-          double2* ring = reinterpret_cast<double2*>((q & 1) ? ring1 : ring0);
-          if (slot < L && sub == 0) ring_sg[q & 1][slot] = (int)ss;
-          if (slot < L) {
-            if constexpr (CPLX) {
+        __syncthreads();
+        ss = (double)rsg[from];
+        if constexpr (CPLX) {
 #pragma unroll
-              for (int j = 0; j < RPL; j++) {
-                ring[(j * 32 + slot) * LPS + sub] = rs[j];
-                ring[((RPL + j) * 32 + slot) * LPS + sub] = ws[j];
+          for (int j = 0; j < RPL; j++) {
+            rs[j] = ring[(j * 32 + from) * LPS + sub];
+            ws[j] = ring[((RPL + j) * 32 + from) * LPS + sub];
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < RPL / 2; j++) {
+            const double2 a = ring[(j * 32 + from) * LPS + sub];
+            const double2 b = ring[((RPL / 2 + j) * 32 + from) * LPS + sub];
+            rs[2 * j] = a.x;
+            rs[2 * j + 1] = a.y;
+            ws[2 * j] = b.x;
+            ws[2 * j + 1] = b.y;
+          }
+        }
+      };
+      int sfin;  // second-block column held by this slot after the last round
+      if (n1 == n2 && (L & (L - 1)) == 0) {
+        int nx = 0;  // LDS exchanges so far (alternate buffers)
+        for (int q = 0; q < L; q++) {
+          if (slot < L) rotate_held();
+          if (q + 1 < L) {
+            const int b = __builtin_ctz(q + 1);
+            const int lx = LPS << b;  // lane distance to the partner slot
+            if (lx == 8) {
+              ss = xor8_of(ss);
+#pragma unroll
+              for (int i = 0; i < RPL; i++) {
+                rs[i] = xor8_of(rs[i]);
+                ws[i] = xor8_of(ws[i]);
+              }
+            } else if (lx < 64) {
+              const int addr = ((tid & 63) ^ lx) << 2;
+              ss = bperm_of(ss, addr);
+#pragma unroll
+              for (int i = 0; i < RPL; i++) {
+                rs[i] = bperm_of(rs[i], addr);
+                ws[i] = bperm_of(ws[i], addr);
               }
             } else {
-#pragma unroll
-              for (int j = 0; j < RPL / 2; j++) {
-                ring[(j * 32 + slot) * LPS + sub] = double2{rs[2 * j], rs[2 * j + 1]};
-                ring[((RPL / 2 + j) * 32 + slot) * LPS + sub] = double2{ws[2 * j], ws[2 * j + 1]};
-              }
+              exchange_lds((nx & 1) ? ring1 : ring0, ring_sg[nx & 1], slot ^ (1 << b));
+              nx++;
             }
           }
-          __syncthreads();
-          if (slot < L) {
+        }
+        sfin = slot ^ (L >> 1);  // gray(L - 1) = L / 2
+      } else {
+        for (int q = 0; q < L; q++) {
+          int sidx = slot + q;  // second-block column held by this slot: (slot + q) mod L
+          if (sidx >= L) sidx -= L;
+          if (slot < L && have_r && sidx < n2) rotate_held();
+          if (q + 1 < L) {
+            // slot k receives the second-block column of slot (k + 1) mod L
             const int from = slot + 1 < L ? slot + 1 : 0;
-            ss = (double)ring_sg[q & 1][from];
-            if constexpr (CPLX) {
-#pragma unroll
-              for (int j = 0; j < RPL; j++) {
-                rs[j] = ring[(j * 32 + from) * LPS + sub];
-                ws[j] = ring[((RPL + j) * 32 + from) * LPS + sub];
-              }
-            } else {
-#pragma unroll
-              for (int j = 0; j < RPL / 2; j++) {
-                const double2 a = ring[(j * 32 + from) * LPS + sub];
-                const double2 b = ring[((RPL / 2 + j) * 32 + from) * LPS + sub];
-                rs[2 * j] = a.x;
-                rs[2 * j + 1] = a.y;
-                ws[2 * j] = b.x;
-                ws[2 * j + 1] = b.y;
-              }
-            }
+            exchange_lds((q & 1) ? ring1 : ring0, ring_sg[q & 1], slot < L ? from : slot);
           }
         }
+        sfin = (slot + L - 1) % L;
       }
       __syncthreads();
-      // write the columns back: slot k holds second-block column (k + L - 1) mod L
-      const int sfin = (slot + L - 1) % L;
+      // write the columns back
 #pragma unroll
       for (int i = 0; i < RPL; i++) {
         const int row = sub + LPS * i;
