@@ -117,20 +117,20 @@ __global__ __launch_bounds__(256) void k_batch_finalize(double* const* __restric
 
 void launch_batch_advance(int count, const int* nsteps, int* step, int* sweep, int* active, int* status,
                           SweepStats* st, double* final_off, int max_sweeps, int* active_count, hipStream_t stream) {
-  hipLaunchKernelGGL(k_batch_advance, dim3((count + 255) / 256), dim3(256), 0, stream, count, nsteps, step, sweep,
+  launch(k_batch_advance, dim3((count + 255) / 256), dim3(256), 0, stream, count, nsteps, step, sweep,
                      active, status, st, final_off, max_sweeps, active_count);
 }
 
 void launch_batch_check_finite(int count, double* const* gptr, const int* ldg, const int* nrow, const int* width,
                                int* bad, hipStream_t stream) {
-  hipLaunchKernelGGL(k_batch_check_finite, dim3(count), dim3(256), 0, stream, gptr, ldg, nrow, width, bad);
+  launch(k_batch_check_finite, dim3(count), dim3(256), 0, stream, gptr, ldg, nrow, width, bad);
 }
 
 void launch_batch_finalize(int count, double* const* gptr, const int* ldg, const int* nrow, const int* width,
                            const int* colmap, const int* cm_off, const signed char* sgn, double* const* lam_ptr,
                            double* const* v_ptr, const int* ldv, double* dwork, int* rkwork, int* zero_col,
                            hipStream_t stream) {
-  hipLaunchKernelGGL(k_batch_finalize, dim3(count), dim3(256), 0, stream, gptr, ldg, nrow, width, colmap, cm_off, sgn,
+  launch(k_batch_finalize, dim3(count), dim3(256), 0, stream, gptr, ldg, nrow, width, colmap, cm_off, sgn,
                      lam_ptr, v_ptr, ldv, dwork, rkwork, zero_col);
 }
 

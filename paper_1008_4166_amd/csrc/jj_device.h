@@ -1,6 +1,7 @@
 // Internal interface between the host orchestrator (jj_solver.hip) and the
 // gfx950 kernels (jj_kernels.hip).  Not part of the public ABI.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -103,6 +104,23 @@ __device__ __forceinline__ void xcd_slot_chunk(int& slot, int& ch) {
   }
   slot = 0;
   ch = 0;  // not reached: the runs cover all T pairs
+}
+
+// Events that the next kernel launch records at its own start and end
+// (per-kernel profiling; the launch takes them and clears the slot).  Launches
+// with no events armed are plain launches, which is what stream capture sees.
+struct LaunchEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+extern thread_local LaunchEvents g_next_launch;
+template <typename F, typename... Args>
+inline void launch(F kernel, const dim3& grid, const dim3& block, unsigned shm, hipStream_t stream, Args... args) {
+  const LaunchEvents ev = g_next_launch;
+  g_next_launch = LaunchEvents();
+  if (ev.start != nullptr)
+    hipExtLaunchKernelGGL(kernel, grid, block, shm, stream, ev.start, ev.stop, 0u, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, shm, stream, args...);
 }
 
 // ---- launchers (all asynchronous on `stream`) ----

@@ -218,13 +218,13 @@ __global__ __launch_bounds__(256) void k_gram_c64mix(const double* __restrict__ 
 
 void launch_gram_f32mix(const double* G, int ldg, int n, const PivotList& pl, int nch, int rows_per_chunk,
                         double* part, hipStream_t stream, const Batch& b) {
-  hipLaunchKernelGGL(k_gram_f32mix, dim3(nch, pl.count), dim3(256), 0, stream, G, ldg, n, pl.cols, pl.m,
+  launch(k_gram_f32mix, dim3(nch, pl.count), dim3(256), 0, stream, G, ldg, n, pl.cols, pl.m,
                      rows_per_chunk, part, b);
 }
 
 void launch_gram_c64mix(const double* G, int ldg, int n, const PivotList& pl, int nch, int rows_per_chunk,
                         double* part, hipStream_t stream, const Batch& b) {
-  hipLaunchKernelGGL(k_gram_c64mix, dim3(nch, pl.count), dim3(256), 0, stream, G, ldg, n, pl.cols, pl.m,
+  launch(k_gram_c64mix, dim3(nch, pl.count), dim3(256), 0, stream, G, ldg, n, pl.cols, pl.m,
                      rows_per_chunk, part, b);
 }
 

@@ -451,45 +451,45 @@ __global__ __launch_bounds__(256) void k_write_v(const double* __restrict__ G, i
 // ---------------------------------------------------------------------------
 void launch_gram_f64(const double* G, int ldg, int n, const PivotList& pl, int nch, int rows_per_chunk,
                      double* part, hipStream_t stream, const Batch& b) {
-  hipLaunchKernelGGL(k_gram_f64, dim3(nch, pl.count), dim3(256), 0, stream, G, ldg, n, pl.cols, pl.m,
+  launch(k_gram_f64, dim3(nch, pl.count), dim3(256), 0, stream, G, ldg, n, pl.cols, pl.m,
                      rows_per_chunk, part, b);
 }
 
 void launch_update_f64(double* G, int ldg, int n, const PivotList& pl, const double* W, const int* rotflag,
                        int rows_per_chunk, hipStream_t stream, const Batch& b, int nch_u) {
   int nch = nch_u > 0 ? nch_u : (n + rows_per_chunk - 1) / rows_per_chunk;
-  hipLaunchKernelGGL(k_update_f64, dim3(nch, pl.count), dim3(256), 0, stream, G, ldg, n, pl.cols, pl.m, W,
+  launch(k_update_f64, dim3(nch, pl.count), dim3(256), 0, stream, G, ldg, n, pl.cols, pl.m, W,
                      rotflag, rows_per_chunk, b);
 }
 
 void launch_gram_c128(const double* G, int ldg, int n, const PivotList& pl, int nch, int rows_per_chunk,
                       double* part, hipStream_t stream, const Batch& b) {
-  hipLaunchKernelGGL(k_gram_c128, dim3(nch, pl.count), dim3(256), 0, stream, G, ldg, n, pl.cols, pl.m,
+  launch(k_gram_c128, dim3(nch, pl.count), dim3(256), 0, stream, G, ldg, n, pl.cols, pl.m,
                      rows_per_chunk, part, b);
 }
 
 void launch_update_c128(double* G, int ldg, int n, const PivotList& pl, const double* W, const int* rotflag,
                         int rows_per_chunk, hipStream_t stream, const Batch& b, int nch_u) {
   int nch = nch_u > 0 ? nch_u : (n + rows_per_chunk - 1) / rows_per_chunk;
-  hipLaunchKernelGGL(k_update_c128, dim3(nch, pl.count), dim3(256), 0, stream, G, ldg, n, pl.cols, pl.m, W,
+  launch(k_update_c128, dim3(nch, pl.count), dim3(256), 0, stream, G, ldg, n, pl.cols, pl.m, W,
                      rotflag, rows_per_chunk, b);
 }
 
 void launch_reset_stats(SweepStats* st, hipStream_t stream) {
-  hipLaunchKernelGGL(k_reset_stats, dim3(1), dim3(64), 0, stream, st);
+  launch(k_reset_stats, dim3(1), dim3(64), 0, stream, st);
 }
 
 void launch_check_finite(const double* G, int ldg, int n, int cplx, SweepStats* st, hipStream_t stream) {
-  hipLaunchKernelGGL(k_check_finite, dim3(n), dim3(256), 0, stream, G, ldg, n, cplx ? 2 : 1, st);
+  launch(k_check_finite, dim3(n), dim3(256), 0, stream, G, ldg, n, cplx ? 2 : 1, st);
 }
 
 void launch_finalize(const double* G, int ldg, int n, int cplx, const int* colmap, const signed char* sgn,
                      double* d, int* rank, double* lambda, double* V, int ldv, SweepStats* st,
                      hipStream_t stream) {
   const int w = cplx ? 2 : 1;
-  hipLaunchKernelGGL(k_colnorm, dim3(n), dim3(256), 0, stream, G, ldg, n, w, colmap, d);
-  hipLaunchKernelGGL(k_rank, dim3((n + 255) / 256), dim3(256), 0, stream, n, d, sgn, colmap, rank, lambda, st);
-  hipLaunchKernelGGL(k_write_v, dim3(n), dim3(256), 0, stream, G, ldg, n, w, colmap, d, rank, V, ldv);
+  launch(k_colnorm, dim3(n), dim3(256), 0, stream, G, ldg, n, w, colmap, d);
+  launch(k_rank, dim3((n + 255) / 256), dim3(256), 0, stream, n, d, sgn, colmap, rank, lambda, st);
+  launch(k_write_v, dim3(n), dim3(256), 0, stream, G, ldg, n, w, colmap, d, rank, V, ldv);
 }
 
 }  // namespace jj

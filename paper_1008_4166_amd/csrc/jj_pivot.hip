@@ -701,14 +701,14 @@ constexpr int kPivotLPS = 8;
 void launch_pivot_f64(const double* part, int nch, int n, int rows_per_chunk, const PivotList& pl, double tol,
                       int inner_max, int inner_mode, int soft, double* W, int* rotflag, SweepStats* st,
                       hipStream_t stream, const Batch& b) {
-  hipLaunchKernelGGL((k_pivot<false, kPivotLPS>), dim3(pl.count), dim3(32 * kPivotLPS), 0, stream, part, nch, n,
+  launch((k_pivot<false, kPivotLPS>), dim3(pl.count), dim3(32 * kPivotLPS), 0, stream, part, nch, n,
                      rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st, b);
 }
 
 void launch_pivot_c128(const double* part, int nch, int n, int rows_per_chunk, const PivotList& pl, double tol,
                        int inner_max, int inner_mode, int soft, double* W, int* rotflag, SweepStats* st,
                        hipStream_t stream, const Batch& b) {
-  hipLaunchKernelGGL((k_pivot<true, kPivotLPS>), dim3(pl.count), dim3(32 * kPivotLPS), 0, stream, part, nch, n,
+  launch((k_pivot<true, kPivotLPS>), dim3(pl.count), dim3(32 * kPivotLPS), 0, stream, part, nch, n,
                      rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st, b);
 }
 

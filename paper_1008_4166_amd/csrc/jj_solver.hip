@@ -30,6 +30,8 @@
 
 namespace jj {
 
+thread_local LaunchEvents g_next_launch;
+
 static thread_local std::string g_last_error;
 static std::mutex g_mutex;
 
@@ -87,6 +89,7 @@ struct Profiler {
     int kind;
     size_t e0, e1;
   };
+
   std::vector<Rec> recs;
   jj_profile acc;
   static std::vector<hipEvent_t>& pool() {
@@ -111,6 +114,26 @@ struct Profiler {
     acc.launches[kind]++;
     acc.units[kind] += units;
   }
+  // A region of exactly one kernel: the launch itself records a pair of events
+  // at its dispatch start and end, so no marker packets sit around it.
+  size_t arm() {
+    if (!on) return 0;
+    auto& P = pool();
+    while (P.size() < used + 2) {
+      hipEvent_t e;
+      ck(hipEventCreate(&e), "hipEventCreate");
+      P.push_back(e);
+    }
+    g_next_launch = LaunchEvents{P[used], P[used + 1]};
+    used += 2;
+    return used - 2;
+  }
+  void done_kernel(int kind, size_t e0, long long units) {
+    if (!on) return;
+    recs.push_back(Rec{kind, e0, e0 + 1});
+    acc.launches[kind]++;
+    acc.units[kind] += units;
+  }
   // call after the stream has been synchronised
   void flush() {
     if (!on) return;
@@ -122,6 +145,18 @@ struct Profiler {
     }
     recs.clear();
     used = 0;
+  }
+};
+
+// Instantiated sweep graphs of one solve, by (precision, diagonal pass);
+// destroyed with the solve.
+struct SweepGraphs {
+  hipGraphExec_t ex[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  hipGraphExec_t& at(bool mix, bool diag) { return ex[mix ? 1 : 0][diag ? 1 : 0]; }
+  ~SweepGraphs() {
+    for (auto& r : ex)
+      for (auto& e : r)
+        if (e != nullptr) hipGraphExecDestroy(e);
   }
 };
 static thread_local jj_profile g_last_prof;
@@ -276,13 +311,43 @@ static void build_diag_tables(const Plan& P, std::vector<int>& cols, std::vector
   }
 }
 
+// The library's own non-blocking stream on the current device: solves run on
+// it (a HIP graph cannot be captured on the legacy default stream), ordered
+// after the caller's stream on entry; on scope exit the caller's stream is
+// ordered after everything the solve enqueued.
+static hipStream_t lib_stream() {
+  static hipStream_t s[64] = {};
+  int dev = 0;
+  ck(hipGetDevice(&dev), "hipGetDevice");
+  if (!s[dev & 63]) ck(hipStreamCreateWithFlags(&s[dev & 63], hipStreamNonBlocking), "hipStreamCreate");
+  return s[dev & 63];
+}
+
+struct StreamJoin {
+  hipStream_t caller, lib;
+  hipEvent_t ev = nullptr;
+  StreamJoin(hipStream_t c, hipStream_t l) : caller(c), lib(l) {
+    if (caller == lib) return;
+    ck(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event");
+    ck(hipEventRecord(ev, caller), "event");
+    ck(hipStreamWaitEvent(lib, ev, 0), "wait event");
+  }
+  ~StreamJoin() {
+    if (ev == nullptr) return;
+    (void)hipEventRecord(ev, lib);
+    (void)hipStreamWaitEvent(caller, ev, 0);
+    (void)hipEventDestroy(ev);
+  }
+};
+
 static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, double* lambda, void* Vv,
-                     int ldv, double tol, int max_sweeps, const jj_opts& o, jj_info* info) {
+                     int ldv, double tol, int max_sweeps, const jj_opts& o, jj_info* info, bool graphs_ok = true) {
   auto t0 = std::chrono::steady_clock::now();
   const int cplx = dtype == JJ_C128;
   double* G = (double*)Gv;
   double* V = (double*)Vv;
-  hipStream_t stream = (hipStream_t)o.stream;
+  hipStream_t stream = lib_stream();
+  StreamJoin join((hipStream_t)o.stream, stream);
   const int nt = o.block_width > 0 ? std::min(o.block_width, kMaxBlock) : 32;
   const int inner_max = o.inner_max_sweeps > 0 ? o.inner_max_sweeps : 12;
   if (tol <= 0.0) tol = (double)n * std::ldexp(1.0, -53);
@@ -396,25 +461,27 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
   double last_off = 0.0;
   bool breakdown = false;
   if (P.nbl < 2) status = JJ_OK;
-  while (P.nbl >= 2 && sweep < max_sweeps) {
-    sweep++;
-    const bool use_mix = mixed;
+  // One sweep: stats reset, the optional diagonal pass, then every step of the
+  // pairing (Gram partials, pivot solves, update).  Profiled solves launch it
+  // eagerly with per-kernel events; otherwise each variant (precision, diagonal
+  // pass) is captured once per solve as a HIP graph and replayed per sweep.
+  auto enqueue_sweep = [&](bool use_mix, bool diag) {
     auto gram = use_mix ? gram32 : gram64;
     const double stol = use_mix ? tol_mix : tol;
-    e0 = prof.mark();
+    size_t k0 = prof.mark();
     launch_reset_stats(d_st, stream);
-    prof.done(JJ_K_OTHER, e0, 0);
-    if (o.diag_pass == 2 || (o.diag_pass == 1 && sweep == 1)) {
+    prof.done(JJ_K_OTHER, k0, 0);
+    if (diag) {
       PivotList dl{d_dcols, d_dsg, d_dm, d_dnf, P.nbl};
-      e0 = prof.mark();
+      k0 = prof.arm();
       gram(G, ldg, n, dl, nch, rows_g, d_part, stream, Batch());
-      prof.done(JJ_K_GRAM, e0, dl.count);
-      e0 = prof.mark();
+      prof.done_kernel(JJ_K_GRAM, k0, dl.count);
+      k0 = prof.arm();
       pivot(d_part, nch, n, rows_g, dl, stol, inner_max, 0, use_mix, d_W, d_rot, d_st, stream, Batch());
-      prof.done(JJ_K_PIVOT, e0, dl.count);
-      e0 = prof.mark();
+      prof.done_kernel(JJ_K_PIVOT, k0, dl.count);
+      k0 = prof.arm();
       update(G, ldg, n, dl, d_W, d_rot, rows_u, stream, Batch(), 0);
-      prof.done(JJ_K_UPDATE, e0, 0);
+      prof.done_kernel(JJ_K_UPDATE, k0, 0);
     }
     for (int t = 0; t < P.nsteps; t++) {
       PivotList pl{d_cols + (size_t)t * h * kMaxPivot, d_sg + (size_t)t * h * kMaxPivot, d_m + (size_t)t * h,
@@ -426,15 +493,42 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
       const bool block_oriented = o.inner_mode == 0;
       const int mode = (block_oriented && t > 0) ? 1 : 0;  // kernel mode 1: off-diagonal pass only
       const int imax = block_oriented ? 1 : inner_max;
-      e0 = prof.mark();
+      k0 = prof.arm();
       gram(G, ldg, n, pl, nch, rows_g, d_part, stream, Batch());
-      prof.done(JJ_K_GRAM, e0, pl.count);
-      e0 = prof.mark();
+      prof.done_kernel(JJ_K_GRAM, k0, pl.count);
+      k0 = prof.arm();
       pivot(d_part, nch, n, rows_g, pl, stol, imax, mode, use_mix, d_W, d_rot, d_st, stream, Batch());
-      prof.done(JJ_K_PIVOT, e0, pl.count);
-      e0 = prof.mark();
+      prof.done_kernel(JJ_K_PIVOT, k0, pl.count);
+      k0 = prof.arm();
       update(G, ldg, n, pl, d_W, d_rot, rows_u, stream, Batch(), 0);
-      prof.done(JJ_K_UPDATE, e0, 0);
+      prof.done_kernel(JJ_K_UPDATE, k0, 0);
+    }
+  };
+  SweepGraphs graphs;
+  while (P.nbl >= 2 && sweep < max_sweeps) {
+    sweep++;
+    const bool use_mix = mixed;
+    const bool diag = o.diag_pass == 2 || (o.diag_pass == 1 && sweep == 1);
+    if (prof.on || !graphs_ok) {
+      enqueue_sweep(use_mix, diag);
+    } else {
+      hipGraphExec_t& ex = graphs.at(use_mix, diag);
+      if (ex == nullptr) {
+        hipGraph_t g = nullptr;
+        ck(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal), "begin capture");
+        try {
+          enqueue_sweep(use_mix, diag);
+        } catch (...) {
+          (void)hipStreamEndCapture(stream, &g);
+          if (g != nullptr) (void)hipGraphDestroy(g);
+          throw;
+        }
+        ck(hipStreamEndCapture(stream, &g), "end capture");
+        const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        ck(ie, "instantiate");
+      }
+      ck(hipGraphLaunch(ex, stream), "graph launch");
     }
     ck(hipGetLastError(), "launch");
     ck(hipMemcpyAsync(&hst, d_st, sizeof(hst), hipMemcpyDeviceToHost, stream), "D2H");
@@ -546,7 +640,7 @@ static int tune_block_width(int dtype, void* G, const signed char* J, int n, int
     o.stream = stream;
     o.block_width = c;
     ck(hipEventRecord(e0, stream), "event");
-    solve_one(dtype, Gc, J, n, n, lam, V, n, 0.0, 2, o, nullptr);
+    solve_one(dtype, Gc, J, n, n, lam, V, n, 0.0, 2, o, nullptr, false);
     ck(hipEventRecord(e1, stream), "event");
     ck(hipEventSynchronize(e1), "event");
     float ms = 0.f;
@@ -564,13 +658,6 @@ static int tune_block_width(int dtype, void* G, const signed char* J, int n, int
   return best;
 }
 
-static hipStream_t batch_stream() {
-  static hipStream_t s[64] = {};
-  int dev = 0;
-  ck(hipGetDevice(&dev), "hipGetDevice");
-  if (!s[dev & 63]) ck(hipStreamCreateWithFlags(&s[dev & 63], hipStreamNonBlocking), "hipStreamCreate");
-  return s[dev & 63];
-}
 
 struct GroupTables {
   std::vector<int> cols, m, nfirst, slot_prob, slot_k;
@@ -724,7 +811,7 @@ static int solve_batch(int count, const int* dtype, void* const* G, const signed
   int* d_rkwork = (int*)ptrs[pi++];
   int* d_active_count = (int*)ptrs[pi++];
 
-  hipStream_t s = batch_stream();
+  hipStream_t s = lib_stream();
   hipEvent_t ev;
   ck(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event");
   ck(hipEventRecord(ev, caller), "event");
