@@ -3,7 +3,8 @@ reordering and partition, block sweeps of Gram / pivot solve / update, and
 the eigenpair finalisation) of the n = 4096 real FP64 workload (J with 3000
 positive entries, |lambda| log-uniform in [1e-12, 1], G = Q diag(sqrt|lambda|) W).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-mixed]
+                    [--no-batched] [--no-c4] [--copy-probe-mb MB]
 
 Prints one JSON line.  value = eigenpairs/s = n * K / (time of K solves), with
 every solve's input G already resident in HBM (one pristine device copy per
@@ -23,6 +24,11 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6  # MFMA and vector
 WORKLOAD = 3
+
+
+def note(msg):
+    """Progress on stderr (stdout carries only the JSON line)."""
+    print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
 def algorithmic_work(prof, n, cplx):
@@ -61,6 +67,42 @@ def algorithmic_work(prof, n, cplx):
     return out
 
 
+def sources_sha256():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1008_4166_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def pmc_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, scaled by the copy-kernel calibration), or None
+    when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_n4096_f64_solve.md")
+    if not os.path.exists(path):
+        return None
+    vals, sha, ff, wf = {}, None, None, None
+    with open(path) as f:
+        for line in f:
+            t = line.split()
+            if len(t) == 2 and t[0] == "sources_sha256":
+                sha = t[1]
+            elif len(t) == 2 and t[0] == "fetch_factor":
+                ff = float(t[1])
+            elif len(t) == 2 and t[0] == "write_factor":
+                wf = float(t[1])
+            elif len(t) == 6 and t[0] == "kernel":
+                vals[t[1]] = (float(t[3]), float(t[5]))
+    if sha != sources_sha256() or kernel not in vals or ff is None or wf is None:
+        return None
+    fk, wk = vals[kernel]
+    return (fk * ff + wk * wf) * 1024.0
+
+
 def roofline(prof, n, cplx):
     work = algorithmic_work(prof, n, cplx)
     kinds = {k: prof[k]["ms"] for k in ("gram", "pivot", "update", "final")}
@@ -79,7 +121,7 @@ def roofline(prof, n, cplx):
             ach = w["flops"] / (w["ms"] * 1e-3) / 1e12
             r = dict(bound="mfma", achieved=ach, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s")
     r["frac"] = r["achieved"] / r["peak"]
-    r["traffic"] = None
+    r["traffic"] = pmc_traffic(dom)
     r["kernel"] = dom
     r["avg_launch_ms"] = w["ms"]
     return r, work
@@ -176,6 +218,56 @@ def bench_batched(jj, torch, count, loop_sample):
                          "|lambda| log-uniform [1e-6, 1e3]" if count == 4096 else "batch of %d" % count)
 
 
+def bench_config4(jj, torch, steps):
+    """n = 8192 complex Hermitian workload (p = 4096, |lambda| log-uniform in
+    [1e-8, 1e2]): plain complex128 solves against the mixed form (FP32-MFMA
+    Gram in the pre-sweeps, complex128 rotations, W_P and update throughout),
+    timed back to back on the same input; accuracy against the prescribed
+    spectrum and between the two forms."""
+    import jjgen
+    t = time.perf_counter()
+    G, J, lam_pres = jjgen.config(4)
+    gen_s = time.perf_counter() - t
+    n = G.shape[0]
+    dev = torch.device("cuda:0")
+    pristine = torch.from_numpy(np.ascontiguousarray(G.T)).to(dev)
+    del G
+    lam = torch.empty(n, dtype=torch.float64, device=dev)
+    Vt = torch.empty((n, n), dtype=torch.complex128, device=dev)
+    stream = torch.cuda.current_stream().cuda_stream
+    ref = np.sort(lam_pres)[::-1]
+    res = {}
+    note("n=8192 complex input generated in %.1f s" % gen_s)
+    for name, extra in (("complex128", {}), ("mixed", dict(precision=1))):
+        o = jj.make_opts(stream=stream, **extra)
+        times, infos = [], []
+        for _ in range(steps):
+            Gw = pristine.clone()
+            info = jj.jj_info()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = jj.jjacobi_solve_ex(jj.JJ_C128, Gw.data_ptr(), J, n, n, lam.data_ptr(), Vt.data_ptr(), n, 0.0, 0,
+                                     o, info)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            if st != 0:
+                raise RuntimeError("n=8192 complex solve status %d" % st)
+            infos.append(info.as_dict())
+            note("n=8192 %s solve: %.2f s, %d sweeps" % (name, times[-1], info.sweeps))
+            del Gw
+        lh = lam.cpu().numpy()
+        res[name] = dict(seconds=min(times), eigenpairs_per_s=n / min(times), sweeps=infos[-1]["sweeps"],
+                         mixed_sweeps=infos[-1]["mixed_sweeps"],
+                         ms_per_sweep=1e3 * min(times) / infos[-1]["sweeps"],
+                         vs_prescribed_max_rel=float(np.max(np.abs(lh - ref) / np.abs(ref))),
+                         inertia_ok=bool(np.sum(lh > 0) == np.sum(J > 0)), lam=lh)
+    a, b = res["complex128"].pop("lam"), res["mixed"].pop("lam")
+    res["mixed"]["vs_complex128_max_rel"] = float(np.max(np.abs(a - b) / np.abs(a)))
+    res["mixed"]["speedup_vs_complex128"] = res["complex128"]["seconds"] / res["mixed"]["seconds"]
+    return dict(workload="n=8192 complex Hermitian, J with 4096 positive, |lambda| log-uniform [1e-8, 1e2]",
+                steps=steps, gen_seconds=gen_s, **res)
+
+
 def stored_oracle(k):
     path = os.path.join(ROOT, "tests", "golden", "config%d_lambda_double.txt" % k)
     if not os.path.exists(path):
@@ -201,6 +293,11 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--loop-sample", type=int, default=64)
+    ap.add_argument("--no-c4", action="store_true", help="skip the n=8192 complex leg")
+    ap.add_argument("--c4-steps", type=int, default=1)
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="before the timed region, one device copy of this many MiB (a reference for "
+                         "hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the solver runs on a single MI355X; "
@@ -220,6 +317,12 @@ def main():
     # G is Fortran-ordered: G.T is C-contiguous with the column-major bytes of G
     pristine = torch.from_numpy(np.ascontiguousarray(G.T)).to(dev)
     K, W = args.steps, args.warmup
+    if args.copy_probe_mb > 0:
+        a = torch.empty(args.copy_probe_mb * 2 ** 20 // 8, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     work = [pristine.clone() for _ in range(K + W)]
     lam = torch.empty(n, dtype=torch.float64, device=dev)
     Vt = torch.empty((n, n), dtype=torch.float64, device=dev)
@@ -242,6 +345,7 @@ def main():
         infos.append(info.as_dict())
         return jj.jjacobi_last_profile() if profiled else None
 
+    note("workload 3 (n=%d) generated in %.1f s; %d warm-up + %d timed solves" % (n, gen_s, W, K))
     for i in range(W):
         step(work[i], False)
     torch.cuda.synchronize()
@@ -298,6 +402,7 @@ def main():
                           for k in ("gram", "pivot", "update", "final", "other")}
         out["inner"] = dict(rotations=pr["rotations"], inner_sweeps=pr["inner_sweeps"])
     # mixed-precision form (FP32-MFMA Gram in pre-sweeps, FP64 rotations, W_P and update)
+    note("timed solves: %.1f ms each" % ms_step)
     if not args.no_mixed:
         mopts = jj.make_opts(stream=stream, block_width=args.block_width, inner_mode=args.inner_mode, precision=1)
         mwork = [pristine.clone() for _ in range(K)]
@@ -321,8 +426,14 @@ def main():
                             mixed_sweeps=[i["mixed_sweeps"] for i in minfos], accuracy=macc,
                             speedup_vs_fp64=ms_step / (dtm / K * 1e3))
     if not args.no_batched:
+        note("batched leg")
         out["batched"] = bench_batched(jj, torch, args.batch_count, args.loop_sample)
+    if not args.no_c4:
+        note("n=8192 complex leg")
+        del work
+        out["config4"] = bench_config4(jj, torch, args.c4_steps)
     if not args.no_cpu:
+        note("cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline(n, oracle_sweeps if oracle_sweeps else 14)
     print(json.dumps(out), flush=True)
 

@@ -80,6 +80,9 @@ typedef struct jj_opts {
                             1: modulus pairing (Section 4.1) */
   int profile;           /* 1: time every kernel launch with HIP events on the stream
                             (read back with jjacobi_last_profile) */
+  double* history;       /* host array or NULL: entry k receives the largest scaled
+                            off-diagonal |a_rs|/sqrt(a_rr a_ss) met in sweep k+1 */
+  int history_len;       /* entries available in history */
   int reserved[7];
 } jj_opts;
 

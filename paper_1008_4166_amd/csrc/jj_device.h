@@ -21,7 +21,7 @@ struct SweepStats {
   int breakdown;                    // Cholesky / hyperbolic-rotation failure seen
   int nonfinite;                    // non-finite value seen in G
   int zero_col;                     // final column norm zero
-  int soft_fail;                    // pivot that could not be factored in a mixed-precision sweep
+  int soft_fail;                    // pivots that could not be factored in a mixed-precision sweep
   unsigned long long rotations;     // plane rotations applied by pivot solves
   unsigned long long inner_sweeps;  // inner sweeps run by pivot solves
   unsigned long long pivot_cols;    // sum of m over pivots that ran the inner solve

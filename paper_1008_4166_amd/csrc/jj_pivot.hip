@@ -398,7 +398,10 @@ __global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ p
   if (s_bad || off <= tol) {
     if (tid == 0) {
       rotflag[bslot] = 0;
-      if (s_bad) atomicOr(soft ? &st->soft_fail : &st->breakdown, 1);
+      if (s_bad) {
+        if (soft) atomicAdd(&st->soft_fail, 1);
+        else atomicOr(&st->breakdown, 1);
+      }
     }
     return;
   }
@@ -437,7 +440,8 @@ __global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ p
     if (s_bad) {
       if (tid == 0) {
         rotflag[bslot] = 0;
-        atomicOr(soft ? &st->soft_fail : &st->breakdown, 1);
+        if (soft) atomicAdd(&st->soft_fail, 1);
+        else atomicOr(&st->breakdown, 1);
       }
       return;
     }
@@ -675,7 +679,10 @@ __global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ p
     if (c_all == 0) break;
     __syncthreads();
   }
-  if (s_bad && tid == 0) atomicOr(soft ? &st->soft_fail : &st->breakdown, 1);
+  if (s_bad && tid == 0) {
+    if (soft) atomicAdd(&st->soft_fail, 1);
+    else atomicOr(&st->breakdown, 1);
+  }
 
   // ---- 5. W_P out ----
   const int rotated = total > 0;

@@ -547,10 +547,13 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
       breakdown = true;
       break;
     }
+    if (o.history != nullptr && sweep <= o.history_len) o.history[sweep - 1] = off;
     if (use_mix) {
-      // leave FP32 Gram blocks once they are accurate enough to finish in FP64, or
-      // when some pivot's FP32 Gram block could not be factored (its scaled
-      // condition number exceeds what FP32 resolves)
+      // leave FP32 Gram blocks once they are accurate enough to finish in FP64,
+      // once no pivot rotates, or as soon as some pivot's FP32 Gram block could
+      // not be factored (its scaled condition exceeds what FP32 resolves: such
+      // pivots, skipped, would otherwise hold the largest off-diagonal at the
+      // same value sweep after sweep)
       mixed_sweeps++;
       if (off < mix_switch || hst.pivots_rotated == 0 || hst.soft_fail) mixed = false;
       continue;
