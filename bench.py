@@ -148,15 +148,16 @@ def cpu_baseline(n_full, sweeps_full):
 def bench_batched(jj, torch, count, loop_sample):
     """Mixed-size batch: `count` matrices, n ~ U{16..512}, half real float64 and
     half complex128, inertia ~ U{0..n}, |lambda| log-uniform in [1e-6, 1e3].
-    One jjacobi_solve_batched call (graph-replayed device step loop) against a
-    loop of single jjacobi_solve_ex calls on an evenly spaced sample."""
-    import ctypes
-
+    One jjacobi_solve_batched call (graph-replayed device step loop) with mixed
+    precision on (FP32-MFMA Gram in each problem's pre-sweeps) and one in plain
+    FP64, each against a loop of single jjacobi_solve_ex calls of the same form
+    on an evenly spaced sample."""
     import jjgen
     specs = jjgen.batch_recipe(count=count)
     t = time.perf_counter()
     flat, offs, Js, lams_pres = jjgen.make_batch(specs)
     gen_s = time.perf_counter() - t
+    note("batch of %d generated in %.1f s" % (count, gen_s))
     dev = torch.device("cuda:0")
     pristine = torch.from_numpy(flat).to(dev)
     work = torch.empty_like(pristine)
@@ -170,50 +171,67 @@ def bench_batched(jj, torch, count, loop_sample):
     Vp = [vbase + 8 * int(o) for o in offs[:-1]]
     Lp = [lbase + 8 * int(o) for o in loff[:-1]]
     stream = torch.cuda.current_stream().cuda_stream
-    opts = jj.make_opts(stream=stream)
-    infos = (jj.jj_info * count)()
+    col2 = []  # squared column norms of every input (trace invariant)
+    for k in range(count):
+        g = flat[offs[k]:offs[k + 1]]
+        c2 = (np.abs(g.view(np.complex128)) ** 2 if specs[k]["cplx"] else g * g).reshape(ns[k], ns[k]).sum(axis=1)
+        col2.append(c2)
+    idx = list(range(0, count, max(1, count // max(1, loop_sample))))[:loop_sample]
+    out, lam_by_form = {}, {}
+    for form, extra in (("mixed", dict(precision=1)), ("fp64", {})):
+        opts = jj.make_opts(stream=stream, **extra)
+        infos = (jj.jj_info * count)()
 
-    def run():
+        def run():
+            work.copy_(pristine)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = jj.jjacobi_solve_batched(count, dts, Gp, Js, ns, ns, Lp, Vp, ns, 0.0, 0, opts, infos)
+            torch.cuda.synchronize()
+            return st, time.perf_counter() - t0
+
+        st_warm, dt_warm = run()  # includes the block-width autotuning of each size bucket (first form)
+        st, dt = run()
+        note("batched %s: %.2f s" % (form, dt))
+        statuses = [infos[k].status for k in range(count)]
+        sweeps = [infos[k].sweeps for k in range(count)]
+        msw = [infos[k].mixed_sweeps for k in range(count)]
+        lam_h = lam.cpu().numpy()
+        lam_by_form[form] = lam_h
+        # invariants of every result: Sylvester inertia and trace(H) = sum_i j_i ||g_i||^2;
+        # accuracy against the prescribed spectrum
+        inertia_bad, tr_err, pres_err = 0, 0.0, []
+        for k in range(count):
+            lk = lam_h[loff[k]:loff[k + 1]]
+            inertia_bad += int(np.sum(lk > 0) != np.sum(Js[k] > 0))
+            tr = float(np.sum(Js[k].astype(float) * col2[k]))
+            tr_err = max(tr_err, abs(float(np.sum(lk)) - tr) / float(np.sum(np.abs(lk))))
+            pres = np.sort(lams_pres[k])[::-1]
+            pres_err.append(float(np.max(np.abs(lk - pres) / np.abs(pres))))
+        # loop of single solves of the same form on the sample, scaled to the whole batch
         work.copy_(pristine)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st = jj.jjacobi_solve_batched(count, dts, Gp, Js, ns, ns, Lp, Vp, ns, 0.0, 0, opts, infos)
+        for k in idx:
+            info = jj.jj_info()
+            jj.jjacobi_solve_ex(dts[k], Gp[k], Js[k], ns[k], ns[k], Lp[k], Vp[k], ns[k], 0.0, 0, opts, info)
         torch.cuda.synchronize()
-        return st, time.perf_counter() - t0
-
-    st_warm, dt_warm = run()  # includes the block-width autotuning of each size bucket
-    st, dt = run()
-    statuses = [infos[k].status for k in range(count)]
-    sweeps = [infos[k].sweeps for k in range(count)]
-    # invariants of every result: Sylvester inertia and trace(H) = sum_i j_i ||g_i||^2
-    lam_h = lam.cpu().numpy()
-    inertia_bad, tr_err = 0, 0.0
-    for k in range(count):
-        lk = lam_h[loff[k]:loff[k + 1]]
-        inertia_bad += int(np.sum(lk > 0) != np.sum(Js[k] > 0))
-        g = flat[offs[k]:offs[k + 1]]
-        col2 = (np.abs(g.view(np.complex128)) ** 2 if specs[k]["cplx"] else g * g).reshape(ns[k], ns[k]).sum(axis=1)
-        tr = float(np.sum(Js[k].astype(float) * col2))
-        tr_err = max(tr_err, abs(float(np.sum(lk)) - tr) / float(np.sum(np.abs(lk))))
-        pres = np.sort(lams_pres[k])[::-1]
-    # loop of single solves on an evenly spaced sample, scaled to the whole batch
-    idx = list(range(0, count, max(1, count // max(1, loop_sample))))[:loop_sample]
-    work.copy_(pristine)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in idx:
-        info = jj.jj_info()
-        jj.jjacobi_solve_ex(dts[k], Gp[k], Js[k], ns[k], ns[k], Lp[k], Vp[k], ns[k], 0.0, 0, opts, info)
-    torch.cuda.synchronize()
-    dt_loop = (time.perf_counter() - t0) * count / len(idx)
-    return dict(metric="batched mats/s", value=count / dt, unit="mats/s", seconds=dt, count=count,
-                worst_status=st, status_counts={str(v): statuses.count(v) for v in set(statuses)},
-                sweeps_max=max(sweeps), sweeps_mean=float(np.mean(sweeps)),
-                loop_of_single_solves=dict(value=count / dt_loop, unit="mats/s", sample=len(idx),
-                                           seconds_scaled=dt_loop),
-                speedup_vs_loop=dt_loop / dt, first_call_seconds_with_tuning=dt_warm,
-                invariants=dict(inertia_mismatches=inertia_bad, max_trace_rel_err=tr_err),
-                gen_seconds=gen_s, gbytes=flat.nbytes / 1e9,
+        dt_loop = (time.perf_counter() - t0) * count / len(idx)
+        out[form] = dict(value=count / dt, seconds=dt, worst_status=st,
+                         status_counts={str(v): statuses.count(v) for v in set(statuses)},
+                         sweeps_max=max(sweeps), sweeps_mean=float(np.mean(sweeps)),
+                         mixed_sweeps_mean=float(np.mean(msw)),
+                         loop_of_single_solves=dict(value=count / dt_loop, unit="mats/s", sample=len(idx),
+                                                    seconds_scaled=dt_loop),
+                         speedup_vs_loop=dt_loop / dt, first_call_seconds=dt_warm,
+                         invariants=dict(inertia_mismatches=inertia_bad, max_trace_rel_err=tr_err),
+                         vs_prescribed_rel=dict(max=max(pres_err), median=float(np.median(pres_err))))
+    a, b = lam_by_form["mixed"], lam_by_form["fp64"]
+    out["mixed"]["vs_fp64_max_rel"] = float(np.max(np.abs(a - b) / np.abs(b)))
+    out["mixed"]["speedup_vs_fp64_batch"] = out["fp64"]["seconds"] / out["mixed"]["seconds"]
+    return dict(metric="batched mats/s (mixed precision on)", value=out["mixed"]["value"], unit="mats/s",
+                count=count, speedup_vs_loop=out["mixed"]["speedup_vs_loop"], gen_seconds=gen_s,
+                gbytes=flat.nbytes / 1e9, mixed=out["mixed"], fp64=out["fp64"],
                 workload="4096 matrices, n ~ U{16..512}, half float64 half complex128, p ~ U{0..n}, "
                          "|lambda| log-uniform [1e-6, 1e3]" if count == 4096 else "batch of %d" % count)
 
@@ -286,7 +304,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--block-width", type=int, default=32)
+    ap.add_argument("--block-width", type=int, default=0, help="0: library choice (tuned)")
     ap.add_argument("--inner-mode", type=int, default=0)
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")

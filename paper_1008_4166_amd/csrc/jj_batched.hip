@@ -10,11 +10,15 @@
 namespace jj {
 
 // After a step: next step of the problem's sweep, or end of the sweep with the
-// convergence test of Section 5.3 (a sweep in which no pivot rotated).
+// convergence test of Section 5.3 (a sweep in which no pivot rotated).  A
+// problem in mixed sweeps never converges in one: it leaves FP32 after a sweep
+// whose largest scaled off-diagonal is below mix_switch, after a sweep with no
+// rotation, or after a sweep in which an FP32 Gram block could not be factored.
 __global__ void k_batch_advance(int count, const int* __restrict__ nsteps, int* __restrict__ step,
                                 int* __restrict__ sweep, int* __restrict__ active, int* __restrict__ status,
                                 SweepStats* __restrict__ st, double* __restrict__ final_off, int max_sweeps,
-                                int* __restrict__ active_count) {
+                                int* __restrict__ active_count, int* __restrict__ prec,
+                                int* __restrict__ mixed_sweeps, double mix_switch) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count || !active[i]) return;
   const int t = step[i] + 1;
@@ -25,11 +29,19 @@ __global__ void k_batch_advance(int count, const int* __restrict__ nsteps, int* 
   const int s = sweep[i] + 1;
   sweep[i] = s;
   SweepStats& c = st[i];
-  final_off[i] = __longlong_as_double((long long)c.max_off_bits);
+  const double off = __longlong_as_double((long long)c.max_off_bits);
+  final_off[i] = off;
   int done = 0, code = 0;
   if (c.breakdown) {
     done = 1;
     code = 2;
+  } else if (prec != nullptr && prec[i]) {
+    mixed_sweeps[i] += 1;
+    if (off < mix_switch || c.pivots_rotated == 0 || c.soft_fail) prec[i] = 0;
+    if (s >= max_sweeps) {
+      done = 1;
+      code = 1;
+    }
   } else if (c.pivots_rotated == 0) {
     done = 1;
     code = 0;
@@ -116,9 +128,10 @@ __global__ __launch_bounds__(256) void k_batch_finalize(double* const* __restric
 }
 
 void launch_batch_advance(int count, const int* nsteps, int* step, int* sweep, int* active, int* status,
-                          SweepStats* st, double* final_off, int max_sweeps, int* active_count, hipStream_t stream) {
-  launch(k_batch_advance, dim3((count + 255) / 256), dim3(256), 0, stream, count, nsteps, step, sweep,
-                     active, status, st, final_off, max_sweeps, active_count);
+                          SweepStats* st, double* final_off, int max_sweeps, int* active_count, int* prec,
+                          int* mixed_sweeps, double mix_switch, hipStream_t stream) {
+  launch(k_batch_advance, dim3((count + 255) / 256), dim3(256), 0, stream, count, nsteps, step, sweep, active,
+         status, st, final_off, max_sweeps, active_count, prec, mixed_sweeps, mix_switch);
 }
 
 void launch_batch_check_finite(int count, double* const* gptr, const int* ldg, const int* nrow, const int* width,

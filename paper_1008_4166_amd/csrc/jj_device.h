@@ -59,6 +59,8 @@ struct Batch {
   const int* nrow = nullptr;      // [problems] rows (= order)
   SweepStats* st = nullptr;       // [problems] counters of the current sweep
   const double* tol = nullptr;    // [problems] rotation threshold
+  const int* prec = nullptr;      // [problems] 1 while the problem runs FP32-Gram (mixed) sweeps
+  int prec_sel = -1;              // Gram launches: serve only problems whose prec equals this (-1: all)
 };
 
 // Resolve a launch slot: pivot-table index, matrix, rows and counters.
@@ -71,6 +73,7 @@ __device__ __forceinline__ bool batch_resolve(const Batch& b, int slot, int& pid
   }
   const int i = b.slot_prob[slot];
   if (!b.active[i]) return false;
+  if (b.prec != nullptr && b.prec_sel >= 0 && b.prec[i] != b.prec_sel) return false;
   pidx = b.tab_base[i] + b.step[i] * b.npairs[i] + b.slot_k[slot];
   G = b.gptr[i];
   ldg = b.ldg[i];
@@ -163,8 +166,12 @@ void launch_update_c128(double* G, int ldg, int n, const PivotList& pl, const do
                         int nch_u = 0);
 
 // Batched bookkeeping (one thread or one workgroup per problem).
+// After a step: next step, or end of sweep with the per-problem convergence
+// test; problems in mixed sweeps (prec[i] = 1, prec may be null) leave FP32 by
+// the same rule as single solves and count their mixed sweeps.
 void launch_batch_advance(int count, const int* nsteps, int* step, int* sweep, int* active, int* status,
-                          SweepStats* st, double* final_off, int max_sweeps, int* active_count, hipStream_t stream);
+                          SweepStats* st, double* final_off, int max_sweeps, int* active_count, int* prec,
+                          int* mixed_sweeps, double mix_switch, hipStream_t stream);
 void launch_batch_check_finite(int count, double* const* gptr, const int* ldg, const int* nrow, const int* width,
                                int* bad, hipStream_t stream);
 void launch_batch_finalize(int count, double* const* gptr, const int* ldg, const int* nrow, const int* width,

@@ -323,6 +323,10 @@ __global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ p
   if (bt.slot_prob != nullptr) {
     const int prob = bt.slot_prob[bslot];
     tol = bt.tol[prob];
+    if (bt.prec != nullptr && bt.prec[prob]) {  // mixed sweep: threshold above FP32 Gram noise
+      tol = fmax(tol, 0x1p-20);
+      soft = 1;
+    }
     if (mode == 2) mode = (bt.step[prob] == 0) ? 0 : 1;  // block-oriented, per problem
   }
   const int m = mlist[p];

@@ -340,6 +340,22 @@ struct StreamJoin {
   }
 };
 
+// Block width chosen per (dtype, size bucket) by timing two sweeps of each
+// candidate on the first problem of that bucket (see tune_block_width).
+static std::map<std::pair<int, int>, int> g_tuned_bw;
+static int size_bucket(int n) {
+  int b = 0;
+  while ((64 << b) < n && b < 12) b++;
+  return b;  // 0: n <= 64, 1: <= 128, 2: <= 256, ...
+}
+static int tune_block_width(int dtype, void* G, const signed char* J, int n, int ldg, hipStream_t stream);
+static int tuned_block_width(int dtype, void* G, const signed char* J, int n, int ldg, hipStream_t stream) {
+  const auto key = std::make_pair(dtype, size_bucket(n));
+  auto it = g_tuned_bw.find(key);
+  if (it == g_tuned_bw.end()) it = g_tuned_bw.emplace(key, tune_block_width(dtype, G, J, n, ldg, stream)).first;
+  return it->second;
+}
+
 static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, double* lambda, void* Vv,
                      int ldv, double tol, int max_sweeps, const jj_opts& o, jj_info* info, bool graphs_ok = true) {
   auto t0 = std::chrono::steady_clock::now();
@@ -348,7 +364,10 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
   double* V = (double*)Vv;
   hipStream_t stream = lib_stream();
   StreamJoin join((hipStream_t)o.stream, stream);
-  const int nt = o.block_width > 0 ? std::min(o.block_width, kMaxBlock) : 32;
+  // block width: the caller's, else tuned for large problems (first use of a
+  // size bucket), else 32
+  int nt = o.block_width > 0 ? std::min(o.block_width, kMaxBlock) : 32;
+  if (o.block_width <= 0 && graphs_ok && n >= 1024) nt = tuned_block_width(dtype, Gv, J, n, ldg, stream);
   const int inner_max = o.inner_max_sweeps > 0 ? o.inner_max_sweeps : 12;
   if (tol <= 0.0) tol = (double)n * std::ldexp(1.0, -53);
   if (max_sweeps <= 0) max_sweeps = 100;
@@ -612,13 +631,7 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
 // Autotuner: block width per (dtype, size bucket), chosen by timing two
 // candidate widths on a copy of the first problem of the bucket (two sweeps
 // each) and cached for the process.
-static std::map<std::pair<int, int>, int> g_tuned_bw;
 
-static int size_bucket(int n) {
-  int b = 0;
-  while ((64 << b) < n && b < 12) b++;
-  return b;  // 0: n <= 64, 1: <= 128, 2: <= 256, ...
-}
 
 static int tune_block_width(int dtype, void* G, const signed char* J, int n, int ldg, hipStream_t stream) {
   const int w = dtype == JJ_C128 ? 2 : 1;
@@ -682,11 +695,7 @@ static int solve_batch(int count, const int* dtype, void* const* G, const signed
       bw[i] = std::min(o.block_width, kMaxBlock);
       continue;
     }
-    auto key = std::make_pair(dtype[i], size_bucket(n[i]));
-    auto it = g_tuned_bw.find(key);
-    if (it == g_tuned_bw.end())
-      it = g_tuned_bw.emplace(key, tune_block_width(dtype[i], G[i], J[i], n[i], ldg[i], caller)).first;
-    bw[i] = it->second;
+    bw[i] = tuned_block_width(dtype[i], G[i], J[i], n[i], ldg[i], caller);
   }
 
   // per-problem plans; tables concatenated per dtype group
@@ -766,6 +775,8 @@ static int solve_batch(int count, const int* dtype, void* const* G, const signed
     take(std::max<size_t>(colmap_all.size(), 1) * sizeof(double));  // dwork
     take(std::max<size_t>(colmap_all.size(), 1) * sizeof(int));     // rkwork
     take(sizeof(int));              // active count
+    take(count * sizeof(int));      // prec (1: mixed sweeps)
+    take(count * sizeof(int));      // mixed sweeps
   };
   std::vector<void*> ptrs;
   layout(c, false, ptrs);
@@ -813,6 +824,8 @@ static int solve_batch(int count, const int* dtype, void* const* G, const signed
   double* d_dwork = (double*)ptrs[pi++];
   int* d_rkwork = (int*)ptrs[pi++];
   int* d_active_count = (int*)ptrs[pi++];
+  int* d_prec = (int*)ptrs[pi++];
+  int* d_msw = (int*)ptrs[pi++];
 
   hipStream_t s = lib_stream();
   hipEvent_t ev;
@@ -882,6 +895,12 @@ static int solve_batch(int count, const int* dtype, void* const* G, const signed
   up(d_active, active.data(), count * sizeof(int));
   up(d_status, status.data(), count * sizeof(int));
   up(d_active_count, &nactive, sizeof(int));
+  // mixed precision (reading as for single solves): FP32-Gram sweeps per problem
+  const bool mixed = o.precision == 1;
+  const double mix_switch = o.mixed_switch > 0.0 ? o.mixed_switch : 1e-5;
+  std::vector<int> prec0(count, mixed ? 1 : 0), msw0(count, 0);
+  up(d_prec, prec0.data(), count * sizeof(int));
+  up(d_msw, msw0.data(), count * sizeof(int));
 
   // rotation threshold per problem: tol, or n * 2^-53 by default
   std::vector<double> ptol(count);
@@ -905,12 +924,21 @@ static int solve_batch(int count, const int* dtype, void* const* G, const signed
     bt[g].nrow = d_nrow;
     bt[g].st = d_st;
     bt[g].tol = d_tol;
+    bt[g].prec = mixed ? d_prec : nullptr;
   }
   auto one_step = [&]() {
     for (int g = 0; g < 2; g++) {
       if (grp[g].slots == 0) continue;
       PivotList pl{dg[g].cols, dg[g].sg, dg[g].m, dg[g].nfirst, grp[g].slots};
-      (g ? launch_gram_c128 : launch_gram_f64)(nullptr, 0, 0, pl, 1, rows_g[g], dg[g].part, s, bt[g]);
+      if (!mixed) {
+        (g ? launch_gram_c128 : launch_gram_f64)(nullptr, 0, 0, pl, 1, rows_g[g], dg[g].part, s, bt[g]);
+      } else {  // FP64 Gram for the problems in FP64 sweeps, FP32-MFMA Gram for the others
+        Batch b64 = bt[g], b32 = bt[g];
+        b64.prec_sel = 0;
+        b32.prec_sel = 1;
+        (g ? launch_gram_c128 : launch_gram_f64)(nullptr, 0, 0, pl, 1, rows_g[g], dg[g].part, s, b64);
+        (g ? launch_gram_c64mix : launch_gram_f32mix)(nullptr, 0, 0, pl, 1, rows_g[g], dg[g].part, s, b32);
+      }
     }
     for (int g = 0; g < 2; g++) {
       if (grp[g].slots == 0) continue;
@@ -924,7 +952,7 @@ static int solve_batch(int count, const int* dtype, void* const* G, const signed
       (g ? launch_update_c128 : launch_update_f64)(nullptr, 0, 0, pl, dg[g].W, dg[g].rot, 256, s, bt[g], nch_u[g]);
     }
     launch_batch_advance(count, d_nsteps, d_step, d_sweep, d_active, d_status, d_st, d_final_off, max_sweeps,
-                         d_active_count, s);
+                         d_active_count, mixed ? d_prec : nullptr, d_msw, mix_switch, s);
   };
 
   // a round of steps captured once, replayed until no problem is active
@@ -952,13 +980,14 @@ static int solve_batch(int count, const int* dtype, void* const* G, const signed
   launch_batch_finalize(count, d_gptr, d_ldg, d_nrow, d_width, d_colmap, d_cm_off, d_sgn, d_lam, d_V, d_ldv, d_dwork,
                         d_rkwork, d_zero, s);
   ck(hipGetLastError(), "launch");
-  std::vector<int> zero(count), sweeps(count);
+  std::vector<int> zero(count), sweeps(count), msw(count);
   std::vector<double> foff(count);
   ck(hipMemcpyAsync(status.data(), d_status, count * sizeof(int), hipMemcpyDeviceToHost, s), "D2H");
   ck(hipMemcpyAsync(active.data(), d_active, count * sizeof(int), hipMemcpyDeviceToHost, s), "D2H");
   ck(hipMemcpyAsync(zero.data(), d_zero, count * sizeof(int), hipMemcpyDeviceToHost, s), "D2H");
   ck(hipMemcpyAsync(sweeps.data(), d_sweep, count * sizeof(int), hipMemcpyDeviceToHost, s), "D2H");
   ck(hipMemcpyAsync(foff.data(), d_final_off, count * sizeof(double), hipMemcpyDeviceToHost, s), "D2H");
+  ck(hipMemcpyAsync(msw.data(), d_msw, count * sizeof(int), hipMemcpyDeviceToHost, s), "D2H");
   ck(hipStreamSynchronize(s), "sync");
   hipEventDestroy(ev);
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -976,6 +1005,7 @@ static int solve_batch(int count, const int* dtype, void* const* G, const signed
       info[i].nblocks = plans[i].nbl;
       info[i].final_offdiag = foff[i];
       info[i].seconds = secs;
+      info[i].mixed_sweeps = msw[i];
     }
   }
   return worst;

@@ -92,3 +92,15 @@ def test_batch_of_workload_sizes():
         assert np.sum(lam > 0) == np.sum(J > 0)
         tr = np.sum(J.astype(float) * np.sum(np.abs(G) ** 2, axis=0))
         assert abs(np.sum(lam) - tr) <= 64 * G.shape[0] * EPS * np.sum(np.abs(lam))
+
+
+def test_mixed_precision_batch_matches_oracle():
+    # FP32-MFMA Gram in each problem's pre-sweeps, FP64 rotations / W_P / update,
+    # FP64 finishing sweeps: the FP64 parity bar for every problem
+    Gs, Js = _mixed_batch(seed=3)
+    lams, Vs, infos, worst = batched(Gs, Js, precision=1)
+    assert worst == 0, [i["status"] for i in infos]
+    assert max(i["mixed_sweeps"] for i in infos) >= 1
+    for G, J, lam, V, info in zip(Gs, Js, lams, Vs, infos):
+        check_parity(G, J, lam, "mixed batched n=%d" % G.shape[0])
+        check_vectors(G, J, lam, V)
