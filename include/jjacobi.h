@@ -85,6 +85,11 @@ typedef struct jj_opts {
   double* history;       /* host array or NULL: entry k receives the largest scaled
                             off-diagonal |a_rs|/sqrt(a_rr a_ss) met in sweep k+1 */
   int history_len;       /* entries available in history */
+  int step_groups;       /* graph-replayed sweeps: 0 or 1 (default): one step after the
+                            other; G > 1: the pairs of a step are split into G groups and
+                            each group's kernels depend only on the groups that last
+                            touched its blocks (groups of consecutive steps may overlap;
+                            same results; slower than 1 with the HIP runtime measured) */
   int reserved[7];
 } jj_opts;
 

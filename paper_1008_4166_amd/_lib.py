@@ -14,6 +14,7 @@ class jj_opts(ctypes.Structure):
                 ("diag_pass", ctypes.c_int), ("inner_mode", ctypes.c_int), ("precision", ctypes.c_int),
                 ("mixed_switch", ctypes.c_double), ("strategy", ctypes.c_int), ("profile", ctypes.c_int),
                 ("history", ctypes.POINTER(ctypes.c_double)), ("history_len", ctypes.c_int),
+                ("step_groups", ctypes.c_int),
                 ("reserved", ctypes.c_int * 7)]
 
 

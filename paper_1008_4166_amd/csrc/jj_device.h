@@ -82,6 +82,18 @@ __device__ __forceinline__ bool batch_resolve(const Batch& b, int slot, int& pid
   return true;
 }
 
+// Global-memory views of a pointer.  Matrices reached through the batch
+// descriptor are pointers loaded from memory, so the compiler sees generic
+// pointers and would emit FLAT accesses (whose completion counts against LDS
+// traffic too); through these views it emits global loads and stores.
+typedef double dv2 __attribute__((ext_vector_type(2)));  // (re, im) of one complex element
+typedef __attribute__((address_space(1))) double gdbl;
+typedef __attribute__((address_space(1))) dv2 gdbl2;
+__device__ __forceinline__ gdbl* as_global(double* p) { return (gdbl*)p; }
+__device__ __forceinline__ const gdbl* as_global(const double* p) { return (const gdbl*)p; }
+__device__ __forceinline__ gdbl2* as_global2(double* p) { return (gdbl2*)p; }
+__device__ __forceinline__ const gdbl2* as_global2(const double* p) { return (const gdbl2*)p; }
+
 // Workgroups of a (chunks x slots) grid placed by XCD.  The dispatcher hands
 // linear workgroup L to XCD L % 8; the pairs (slot, chunk), ordered by
 // (slot % 8, slot / 8, chunk), are cut into consecutive runs, one per XCD, so

@@ -37,14 +37,14 @@ __global__ __launch_bounds__(256) void k_gram_f32mix(const double* __restrict__ 
   SweepStats* stp = nullptr;
   if (!batch_resolve(bt, slot, p, Gm, ldg, n, stp)) return;
   if (ch > 0 && ch * rows_per_chunk >= n) return;  // chunk beyond this problem's rows
-  const double* G = Gm;
+  const gdbl* G = as_global(Gm);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int c16 = lane & 15, g = lane >> 4;
   const int m = mlist[p];
   const int nt = (m + 15) >> 4;
   const int r0 = ch * rows_per_chunk;
   const int r1 = min(n, r0 + rows_per_chunk);
-  const double* cp[4];
+  const gdbl* cp[4];
 #pragma unroll
   for (int J = 0; J < 4; J++) {
     int c = J * 16 + c16;
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(256) void k_gram_f32mix(const double* __restrict__ 
 }
 
 // Complex: Re A = Xr^T Xr + Xi^T Xi, Im A = Xr^T Xi - Xi^T Xr on FP32 MFMA.
-__global__ __launch_bounds__(256) void k_gram_c64mix(const double* __restrict__ G0, int ldg0, int n0,
+__global__ __launch_bounds__(256, 2) void k_gram_c64mix(const double* __restrict__ G0, int ldg0, int n0,
                                                      const int* __restrict__ cols, const int* __restrict__ mlist,
                                                      int rows_per_chunk, double* __restrict__ part, Batch bt) {
   __shared__ d4m red[10][2][64];
@@ -130,19 +130,19 @@ __global__ __launch_bounds__(256) void k_gram_c64mix(const double* __restrict__ 
   SweepStats* stp = nullptr;
   if (!batch_resolve(bt, slot, p, Gm, ldg, n, stp)) return;
   if (ch > 0 && ch * rows_per_chunk >= n) return;  // chunk beyond this problem's rows
-  const double* G = Gm;
+  const gdbl2* G = as_global2(Gm);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int c16 = lane & 15, g = lane >> 4;
   const int m = mlist[p];
   const int nt = (m + 15) >> 4;
   const int r0 = ch * rows_per_chunk;
   const int r1 = min(n, r0 + rows_per_chunk);
-  const double2* cp[4];
+  const gdbl2* cp[4];
 #pragma unroll
   for (int J = 0; J < 4; J++) {
     int c = J * 16 + c16;
     int pc = (c < m) ? cols[p * kMaxPivot + c] : -1;
-    cp[J] = (pc >= 0) ? reinterpret_cast<const double2*>(G) + (size_t)pc * ldg : nullptr;
+    cp[J] = (pc >= 0) ? G + (size_t)pc * ldg : nullptr;
   }
   f4 are[10], aim[10];
 #pragma unroll
@@ -157,7 +157,7 @@ __global__ __launch_bounds__(256) void k_gram_c64mix(const double* __restrict__ 
       float xr[4], xi[4];
 #pragma unroll
       for (int J = 0; J < 4; J++) {
-        double2 v = (cp[J] != nullptr && row < r1) ? cp[J][row] : double2{0.0, 0.0};
+        const dv2 v = (cp[J] != nullptr && row < r1) ? cp[J][row] : dv2{0.0, 0.0};
         xr[J] = (float)v.x;
         xi[J] = (float)v.y;
       }

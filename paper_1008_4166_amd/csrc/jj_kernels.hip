@@ -33,7 +33,7 @@ __device__ __forceinline__ void atomic_max_nonneg(unsigned long long* addr, doub
 // are rows {4g + kk}.  All upper tiles (I <= J) of the 64x64 partial are
 // accumulated; the four waves are reduced through LDS in a fixed order.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_gram_f64(const double* __restrict__ G0, int ldg0, int n0,
+__global__ __launch_bounds__(256, 3) void k_gram_f64(const double* __restrict__ G0, int ldg0, int n0,
                                                   const int* __restrict__ cols, const int* __restrict__ mlist,
                                                   int rows_per_chunk, double* __restrict__ part, Batch bt) {
   __shared__ d4 red[2][10][64];
@@ -45,7 +45,7 @@ __global__ __launch_bounds__(256) void k_gram_f64(const double* __restrict__ G0,
   SweepStats* stp = nullptr;
   if (!batch_resolve(bt, slot, p, Gm, ldg, n, stp)) return;
   if (ch > 0 && ch * rows_per_chunk >= n) return;  // chunk beyond this problem's rows
-  const double* G = Gm;
+  const gdbl* G = as_global(Gm);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int c16 = lane & 15, g = lane >> 4;
   const int m = mlist[p];
@@ -53,7 +53,7 @@ __global__ __launch_bounds__(256) void k_gram_f64(const double* __restrict__ G0,
   const int r0 = ch * rows_per_chunk;
   const int r1 = min(n, r0 + rows_per_chunk);
 
-  const double* cp[4];
+  const gdbl* cp[4];
 #pragma unroll
   for (int J = 0; J < 4; J++) {
     int c = J * 16 + c16;
@@ -133,8 +133,11 @@ __global__ __launch_bounds__(256) void k_gram_f64(const double* __restrict__ G0,
 // consecutive rows of one column (coalesced stores).  A wave loads its whole
 // 16-row strip (all m columns) before writing any of it.
 // ---------------------------------------------------------------------------
-constexpr int LDR = kMaxPivot + 1;
-constexpr int LDW = kMaxPivot + 1;
+// W_P in LDS, column stride 68: an MFMA operand read has lanes (c16, g) at
+// column 16I + c16, row 4kk + g, i.e. word offset 2 (68 c16 + g) = 8 c16 + 2g
+// (mod 64 banks), so 8-byte reads spread evenly over the banks (16-byte
+// complex reads too: 16 c16 + 4g).
+constexpr int LDW = kMaxPivot + 4;
 
 __global__ __launch_bounds__(256) void k_update_f64(double* __restrict__ G0, int ldg0, int n0,
                                                     const int* __restrict__ cols, const int* __restrict__ mlist,
@@ -143,11 +146,12 @@ __global__ __launch_bounds__(256) void k_update_f64(double* __restrict__ G0, int
   int slot, ch;
   xcd_slot_chunk(slot, ch);
   int p = slot, ldg = ldg0, n = n0;
-  double* G = G0;
+  double* Gm = G0;
   SweepStats* stp = nullptr;
-  if (!batch_resolve(bt, slot, p, G, ldg, n, stp)) return;
+  if (!batch_resolve(bt, slot, p, Gm, ldg, n, stp)) return;
   if (!rotflag[slot]) return;
   if (ch * rows_per_chunk >= n) return;
+  gdbl* G = as_global(Gm);
   __shared__ double Ws[kMaxPivot * LDW];
   __shared__ int scol[kMaxPivot];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -206,7 +210,7 @@ __global__ __launch_bounds__(256) void k_update_f64(double* __restrict__ G0, int
 // Complex Hermitian (complex128, interleaved).  A = X^H X is formed from real
 // MFMA products: Re A = Xr^T Xr + Xi^T Xi, Im A = Xr^T Xi - Xi^T Xr.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_gram_c128(const double* __restrict__ G0, int ldg0, int n0,
+__global__ __launch_bounds__(256, 2) void k_gram_c128(const double* __restrict__ G0, int ldg0, int n0,
                                                    const int* __restrict__ cols, const int* __restrict__ mlist,
                                                    int rows_per_chunk, double* __restrict__ part, Batch bt) {
   __shared__ d4 red[10][2][64];
@@ -218,19 +222,19 @@ __global__ __launch_bounds__(256) void k_gram_c128(const double* __restrict__ G0
   SweepStats* stp = nullptr;
   if (!batch_resolve(bt, slot, p, Gm, ldg, n, stp)) return;
   if (ch > 0 && ch * rows_per_chunk >= n) return;  // chunk beyond this problem's rows
-  const double* G = Gm;
+  const gdbl2* G = as_global2(Gm);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int c16 = lane & 15, g = lane >> 4;
   const int m = mlist[p];
   const int nt = (m + 15) >> 4;
   const int r0 = ch * rows_per_chunk;
   const int r1 = min(n, r0 + rows_per_chunk);
-  const double2* cp[4];
+  const gdbl2* cp[4];
 #pragma unroll
   for (int J = 0; J < 4; J++) {
     int c = J * 16 + c16;
     int pc = (c < m) ? cols[p * kMaxPivot + c] : -1;
-    cp[J] = (pc >= 0) ? reinterpret_cast<const double2*>(G) + (size_t)pc * ldg : nullptr;
+    cp[J] = (pc >= 0) ? G + (size_t)pc * ldg : nullptr;
   }
   d4 are[10], aim[10];
 #pragma unroll
@@ -245,7 +249,7 @@ __global__ __launch_bounds__(256) void k_gram_c128(const double* __restrict__ G0
       double xr[4], xi[4];
 #pragma unroll
       for (int J = 0; J < 4; J++) {
-        double2 v = (cp[J] != nullptr && row < r1) ? cp[J][row] : double2{0.0, 0.0};
+        const dv2 v = (cp[J] != nullptr && row < r1) ? cp[J][row] : dv2{0.0, 0.0};
         xr[J] = v.x;
         xi[J] = v.y;
       }
@@ -301,16 +305,16 @@ __global__ __launch_bounds__(256) void k_gram_c128(const double* __restrict__ G0
 
 // Update, complex: D^T = W^T X^T with Re = Wr^T Xr^T - Wi^T Xi^T and
 // Im = Wi^T Xr^T + Wr^T Xi^T.
-__global__ __launch_bounds__(256) void k_update_c128(double* __restrict__ G0, int ldg0, int n0,
+__global__ __launch_bounds__(256, 2) void k_update_c128(double* __restrict__ G0, int ldg0, int n0,
                                                      const int* __restrict__ cols, const int* __restrict__ mlist,
                                                      const double* __restrict__ Wg, const int* __restrict__ rotflag,
                                                      int rows_per_chunk, Batch bt) {
   int slot, ch;
   xcd_slot_chunk(slot, ch);
   int p = slot, ldg = ldg0, n = n0;
-  double* G = G0;
+  double* Gm = G0;
   SweepStats* stp = nullptr;
-  if (!batch_resolve(bt, slot, p, G, ldg, n, stp)) return;
+  if (!batch_resolve(bt, slot, p, Gm, ldg, n, stp)) return;
   if (!rotflag[slot]) return;
   if (ch * rows_per_chunk >= n) return;
   __shared__ double2 Ws[kMaxPivot * LDW];
@@ -327,40 +331,50 @@ __global__ __launch_bounds__(256) void k_update_c128(double* __restrict__ G0, in
   }
   if (tid < kMaxPivot) scol[tid] = (tid < m) ? cols[p * kMaxPivot + tid] : -1;
   __syncthreads();
-  double2* Gc = reinterpret_cast<double2*>(G);
+  gdbl2* Gc = as_global2(Gm);
   const int r0 = ch * rows_per_chunk;
   const int r1 = min(n, r0 + rows_per_chunk);
-  for (int row0 = r0 + wave * 16; row0 < r1; row0 += 64) {
-    const int row = row0 + c16;
-    double xr[16], xi[16];
+  int pcol[16];
 #pragma unroll
-    for (int kk = 0; kk < 16; kk++) {
-      int pc = scol[4 * kk + g];
-      double2 v = (kk < ks && pc >= 0 && row < r1) ? Gc[(size_t)pc * ldg + row] : double2{0.0, 0.0};
-      xr[kk] = v.x;
-      xi[kk] = v.y;
-    }
+  for (int kk = 0; kk < 16; kk++) pcol[kk] = scol[4 * kk + g];
+  // the next strip's loads are issued before the current strip's MFMAs
+  dv2 x[16], xn[16];
+  int row0 = r0 + wave * 16;
+#pragma unroll
+  for (int kk = 0; kk < 16; kk++) {
+    const int row = row0 + c16;
+    x[kk] = (kk < ks && pcol[kk] >= 0 && row < r1) ? Gc[(size_t)pcol[kk] * ldg + row] : dv2{0.0, 0.0};
+  }
+  for (; row0 < r1; row0 += 64) {
+    const int row = row0 + c16;
+    const int nrow = row + 64;
+#pragma unroll
+    for (int kk = 0; kk < 16; kk++)
+      xn[kk] = (kk < ks && pcol[kk] >= 0 && nrow < r1) ? Gc[(size_t)pcol[kk] * ldg + nrow] : dv2{0.0, 0.0};
+    // three real products per complex one (Gauss): T1 = Xr Wr, T2 = Xi Wi,
+    // T3 = (Xr + Xi)(Wr + Wi); Re = T1 - T2, Im = T3 - T1 - T2 (transposed here)
 #pragma unroll
     for (int I = 0; I < 4; I++) {
       if (I < nt) {
-        d4 ar = d4{0.0, 0.0, 0.0, 0.0}, ai = d4{0.0, 0.0, 0.0, 0.0};
+        d4 t1 = d4{0.0, 0.0, 0.0, 0.0}, t2 = d4{0.0, 0.0, 0.0, 0.0}, t3 = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int kk = 0; kk < 16; kk++)
           if (kk < ks) {
-            double2 w = Ws[(16 * I + c16) * LDW + 4 * kk + g];
-            ar = mfma16(w.x, xr[kk], ar);
-            ar = mfma16(-w.y, xi[kk], ar);
-            ai = mfma16(w.y, xr[kk], ai);
-            ai = mfma16(w.x, xi[kk], ai);
+            const double2 w = Ws[(16 * I + c16) * LDW + 4 * kk + g];
+            t1 = mfma16(w.x, x[kk].x, t1);
+            t2 = mfma16(w.y, x[kk].y, t2);
+            t3 = mfma16(w.x + w.y, x[kk].x + x[kk].y, t3);
           }
 #pragma unroll
         for (int v = 0; v < 4; v++) {
           int oc = 16 * I + 4 * v + g;
           int pc = scol[oc];
-          if (oc < m && row < r1) Gc[(size_t)pc * ldg + row] = double2{ar[v], ai[v]};
+          if (oc < m && row < r1) Gc[(size_t)pc * ldg + row] = dv2{t1[v] - t2[v], (t3[v] - t1[v]) - t2[v]};
         }
       }
     }
+#pragma unroll
+    for (int kk = 0; kk < 16; kk++) x[kk] = xn[kk];
   }
 }
 

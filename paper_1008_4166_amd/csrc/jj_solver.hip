@@ -234,6 +234,7 @@ void plan_sign_order(int n, const signed char* J, int* colmap) {
 struct Plan {
   int n, nbl, nsteps, npairs_max;
   std::vector<int> off, colmap, cols, m, nfirst, count;
+  std::vector<int> pblocks;  // [(step * npairs_max + pair) * 2 + {0, 1}]: the pair's two blocks
   std::vector<signed char> sgp, sgn;
 };
 
@@ -246,9 +247,12 @@ static void build_pairs_tables(Plan& P, const std::vector<int>& pairs, int nstep
   P.m.assign((size_t)nsteps * h, 0);
   P.nfirst.assign((size_t)nsteps * h, 0);
   P.count = counts;
+  P.pblocks.assign((size_t)nsteps * h * 2, -1);
   for (int t = 0; t < nsteps; t++)
     for (int k = 0; k < counts[t]; k++) {
       int bi = pairs[(t * h + k) * 2], bj = pairs[(t * h + k) * 2 + 1];
+      P.pblocks[((size_t)t * h + k) * 2] = bi;
+      P.pblocks[((size_t)t * h + k) * 2 + 1] = bj;
       size_t base = ((size_t)t * h + k) * kMaxPivot;
       int c = 0;
       for (int q = P.off[bi]; q < P.off[bi + 1]; q++, c++) {
@@ -322,6 +326,8 @@ static hipStream_t lib_stream() {
   if (!s[dev & 63]) ck(hipStreamCreateWithFlags(&s[dev & 63], hipStreamNonBlocking), "hipStreamCreate");
   return s[dev & 63];
 }
+
+constexpr int kMaxStepGroups = 8;
 
 struct StreamJoin {
   hipStream_t caller, lib;
@@ -523,6 +529,98 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
       prof.done_kernel(JJ_K_UPDATE, k0, 0);
     }
   };
+  // Dataflow form of a sweep.  The pairs of each step are split into G
+  // contiguous groups (tasks: Gram, pivot solve, update of the group's pairs).
+  // The sweep is captured in the sequential order on one stream, which makes a
+  // chain of kernel nodes; the chain edges between tasks are then replaced by
+  // the true dependencies: a task follows the tasks that last touched its
+  // blocks.  Groups of consecutive steps then overlap in the graph (a group's
+  // latency-bound pivot solves run beside other groups' Gram and update
+  // kernels), and every task still reads exactly the data the sequential order
+  // gives it, so the results are those of the eager sweep.
+  const int wsz = cplx ? 2 : 1;
+  const int ngrp = (o.step_groups <= 1 || h < 8) ? 1 : std::min(o.step_groups, std::min(h / 4, kMaxStepGroups));
+  struct Task {
+    hipGraphNode_t first, last;
+    std::vector<int> deps;
+  };
+  auto last_node = [&]() -> hipGraphNode_t {
+    hipStreamCaptureStatus cs;
+    unsigned long long id = 0;
+    hipGraph_t cg = nullptr;
+    const hipGraphNode_t* leaf = nullptr;
+    size_t nleaf = 0;
+    ck(hipStreamGetCaptureInfo_v2(stream, &cs, &id, &cg, &leaf, &nleaf), "capture info");
+    if (cs != hipStreamCaptureStatusActive || nleaf != 1) ck(hipErrorUnknown, "capture: not a single chain");
+    return leaf[0];
+  };
+  // captures the sequential sweep and returns its tasks (root node in *reset)
+  auto capture_sweep_tasks = [&](bool use_mix, bool diag, hipGraphNode_t* reset, std::vector<Task>& tasks) {
+    auto gram = use_mix ? gram32 : gram64;
+    const double stol = use_mix ? tol_mix : tol;
+    launch_reset_stats(d_st, stream);
+    *reset = last_node();
+    std::vector<int> owner(P.nbl, -1);  // last task to touch each block
+    auto run_task = [&](const std::vector<int>& blocks, PivotList pl, size_t s0, int mode, int imax) {
+      Task tk;
+      for (int b : blocks)
+        if (owner[b] >= 0) tk.deps.push_back(owner[b]);
+      std::sort(tk.deps.begin(), tk.deps.end());
+      tk.deps.erase(std::unique(tk.deps.begin(), tk.deps.end()), tk.deps.end());
+      double* part = d_part + s0 * nch * kMaxPivot * kMaxPivot * wsz;
+      double* W = d_W + s0 * kMaxPivot * kMaxPivot * wsz;
+      int* rot = d_rot + s0;
+      gram(G, ldg, n, pl, nch, rows_g, part, stream, Batch());
+      tk.first = last_node();
+      pivot(part, nch, n, rows_g, pl, stol, imax, mode, use_mix, W, rot, d_st, stream, Batch());
+      update(G, ldg, n, pl, W, rot, rows_u, stream, Batch(), 0);
+      tk.last = last_node();
+      for (int b : blocks) owner[b] = (int)tasks.size();
+      tasks.push_back(std::move(tk));
+    };
+    if (diag) {
+      const int q = (P.nbl + ngrp - 1) / ngrp;
+      for (int g = 0; g < ngrp; g++) {
+        const int s0 = g * q, cnt = std::min(P.nbl, s0 + q) - s0;
+        if (cnt <= 0) continue;
+        std::vector<int> blocks;
+        for (int l = s0; l < s0 + cnt; l++) blocks.push_back(l);
+        PivotList dl{d_dcols + (size_t)s0 * kMaxPivot, d_dsg + (size_t)s0 * kMaxPivot, d_dm + s0, d_dnf + s0, cnt};
+        run_task(blocks, dl, s0, 0, inner_max);
+      }
+    }
+    const bool block_oriented = o.inner_mode == 0;
+    const int imax = block_oriented ? 1 : inner_max;
+    for (int t = 0; t < P.nsteps; t++) {
+      const int count = P.count[t];
+      const int q = (count + ngrp - 1) / ngrp;
+      const int mode = (block_oriented && t > 0) ? 1 : 0;
+      for (int g = 0; g < ngrp; g++) {
+        const int s0 = g * q, cnt = std::min(count, s0 + q) - s0;
+        if (cnt <= 0) continue;
+        std::vector<int> blocks;
+        for (int k = s0; k < s0 + cnt; k++) {
+          blocks.push_back(P.pblocks[((size_t)t * h + k) * 2]);
+          blocks.push_back(P.pblocks[((size_t)t * h + k) * 2 + 1]);
+        }
+        const size_t base = (size_t)t * h + s0;
+        PivotList pl{d_cols + base * kMaxPivot, d_sg + base * kMaxPivot, d_m + base, d_nf + base, cnt};
+        run_task(blocks, pl, s0, mode, imax);
+      }
+    }
+  };
+  // chain edges between consecutive tasks -> dependency edges
+  auto rewire = [&](hipGraph_t g, hipGraphNode_t reset, const std::vector<Task>& tasks) {
+    for (size_t i = 0; i < tasks.size(); i++) {
+      const hipGraphNode_t prev = i == 0 ? reset : tasks[i - 1].last;
+      ck(hipGraphRemoveDependencies(g, &prev, &tasks[i].first, 1), "remove edge");
+      if (tasks[i].deps.empty()) {
+        ck(hipGraphAddDependencies(g, &reset, &tasks[i].first, 1), "add edge");
+      } else {
+        for (int d : tasks[i].deps) ck(hipGraphAddDependencies(g, &tasks[d].last, &tasks[i].first, 1), "add edge");
+      }
+    }
+  };
   SweepGraphs graphs;
   while (P.nbl >= 2 && sweep < max_sweeps) {
     sweep++;
@@ -534,15 +632,28 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
       hipGraphExec_t& ex = graphs.at(use_mix, diag);
       if (ex == nullptr) {
         hipGraph_t g = nullptr;
+        hipGraphNode_t reset = nullptr;
+        std::vector<Task> tasks;
         ck(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal), "begin capture");
         try {
-          enqueue_sweep(use_mix, diag);
+          if (ngrp > 1)
+            capture_sweep_tasks(use_mix, diag, &reset, tasks);
+          else
+            enqueue_sweep(use_mix, diag);
         } catch (...) {
           (void)hipStreamEndCapture(stream, &g);
           if (g != nullptr) (void)hipGraphDestroy(g);
           throw;
         }
         ck(hipStreamEndCapture(stream, &g), "end capture");
+        if (ngrp > 1) {
+          try {
+            rewire(g, reset, tasks);
+          } catch (...) {
+            (void)hipGraphDestroy(g);
+            throw;
+          }
+        }
         const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         ck(ie, "instantiate");
@@ -1036,7 +1147,7 @@ extern "C" {
 void jjacobi_default_opts(jj_opts* o) {
   if (!o) return;
   std::memset(o, 0, sizeof(*o));
-  o->block_width = 32;
+  o->block_width = 0;  // library choice (tuned where it matters)
   o->inner_max_sweeps = 12;
   o->mixed_switch = 1e-5;
 }

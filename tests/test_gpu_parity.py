@@ -223,3 +223,16 @@ def test_graph_replay_equals_eager(cplx):
     assert np.array_equal(lam2.cpu().numpy(), lg)
     lg2, Vg2, _ = gpu_solve(G, J)
     assert np.array_equal(lg2, lg) and np.array_equal(Vg2, Vg)
+
+
+@pytest.mark.parametrize("groups", [2, 4])
+def test_dataflow_sweep_graph_equals_eager(groups):
+    # sweeps whose graph keeps only the block-ownership dependencies between
+    # groups of pairs: the same data reaches every kernel, so the results are
+    # bitwise those of the eager (profiled) sweep
+    G, J, _ = jjgen.make(600, False, 250, 1e-8, 1.0, seed=777)
+    lg, Vg, ig = gpu_solve(G, J, block_width=16, step_groups=groups)
+    le, Ve, ie = gpu_solve(G, J, block_width=16, profile=1)
+    assert ig["status"] == 0 and ig["sweeps"] == ie["sweeps"]
+    assert np.array_equal(lg, le) and np.array_equal(Vg, Ve)
+    check_parity(G, J, lg, "dataflow groups=%d" % groups)
