@@ -108,6 +108,19 @@ __device__ __forceinline__ double sqrt_nr(double x) {
   const double y = x * rsqrt_nr(fmax(x, 1e-300));
   return x > 0.0 ? y : 0.0;
 }
+// One Newton step only (relative error about 2^-46): for t, whose rounding
+// decides how far a rotation reduces its pair, not the J-unitarity of the
+// rotation (cs and sn are formed from the t actually used).
+__device__ __forceinline__ double rcp_nr1(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ double sqrt_nr1(double x) {
+  const double d = fmax(x, 1e-300);
+  double y = __builtin_amdgcn_rsq(d);
+  y = fma(0.5 * y, fma(-(d * y), y, 1.0), y);
+  return x > 0.0 ? x * y : 0.0;
+}
 
 // Rotation for the 2x2 pivot [arr eta; eta ass] (eta real) with sigma = +j_r j_s
 // (Algorithm 3.1 read with sigma = +j_r j_s).  With N = sigma a_ss - a_rr
@@ -117,22 +130,28 @@ __device__ __forceinline__ double sqrt_nr(double x) {
 // 1 - t^2 = (1-|t|)(1+|t|), and sn = cs t, so that the applied rotation is
 // J-unitary to working precision whatever the rounding of t.  The hyperbolic
 // rotation exists iff |N| > 2|eta|.
-// Returns 0: below tol, 1: (cs, sn) set, -1: hyperbolic breakdown.
+// Returns 0: below tol, 1: (cs, sn) set, -1: hyperbolic breakdown (cs and sn
+// are meaningful only for 1).
+// The threshold test |eta| > tol sqrt(a_rr) sqrt(a_ss) uses the hardware
+// reciprocal-square-root estimates (an error of 2^-23 can only change the
+// decision for a pair lying at the threshold) and is evaluated beside the
+// rotation instead of before it: the dependent chain of a round is the
+// rotation alone.
 __device__ __forceinline__ int rot_params(double arr, double ass, double eta, double sigma, double tol,
                                           double* cs, double* sn) {
-  if (!(fabs(eta) > tol * (sqrt_nr(arr) * sqrt_nr(ass)))) return 0;
+  const bool above = fabs(eta) * (__builtin_amdgcn_rsq(arr) * __builtin_amdgcn_rsq(ass)) > tol;
   const double N = sigma * ass - arr;
   const double e2 = 2.0 * fabs(eta);
-  if (sigma < 0.0 && fabs(N) <= e2) return -1;
+  const bool no_hyp = sigma < 0.0 && fabs(N) <= e2;
   const int ex = ilogb(fmax(fabs(N), e2));
   const double Ns = ldexp(N, -ex), Es = ldexp(e2, -ex);
-  double t = Es * rcp_nr(fabs(Ns) + sqrt_nr(fma(Ns, Ns, sigma * (Es * Es))));
+  double t = Es * rcp_nr1(fabs(Ns) + sqrt_nr1(fma(Ns, Ns, sigma * (Es * Es))));
   if ((N < 0.0) != (eta < 0.0)) t = -t;
   const double at = fabs(t);
   const double c = rsqrt_nr(sigma > 0.0 ? fma(t, t, 1.0) : (1.0 - at) * (1.0 + at));
   *cs = c;
   *sn = c * t;
-  return 1;
+  return !above ? 0 : (no_hyp ? -1 : 1);
 }
 
 // Move a double across lanes with a DPP pattern (both 32-bit halves).
@@ -296,14 +315,15 @@ __device__ __forceinline__ void chol_trailing(double2* R, int r0, int m, int lan
 }
 
 template <bool CPLX, int LPS>
-__global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ part, int nch, int n0,
+__global__ __launch_bounds__(64 * LPS) void k_pivot(const double* __restrict__ part, int nch, int n0,
                                                     int rows_per_chunk, const int* __restrict__ mlist,
                                                     const int* __restrict__ nfirst,
                                                     const signed char* __restrict__ sgl, double tol, int inner_max,
                                                     int mode, int soft, double* __restrict__ Wout,
                                                     int* __restrict__ rotflag, SweepStats* st0, Batch bt) {
   typedef typename Scalar<CPLX>::T T;
-  constexpr int NT = 32 * LPS;
+  constexpr int NT = 64 * LPS;  // two halves of 32 slots
+  constexpr int HT = 32 * LPS;  // threads of one half
   constexpr int RPL = kMaxPivot / LPS;  // rows of one column held by a lane
   __shared__ T lds[2 * kMaxPivot * LDR];
   __shared__ double redv[NT / 64];
@@ -311,6 +331,8 @@ __global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ p
   __shared__ int s_cnt, s_bad;
   __shared__ signed char s_sg[kMaxPivot];
   __shared__ int ring_sg[2][32];
+  __shared__ double prm[2][32][5];  // rotation of each slot in a cross round: cs, sn, -sigma sn, phase
+  __shared__ int prc[2][32];        // 1: that rotation is applied
   T* R = lds;
   T* W = lds + kMaxPivot * LDR;
   const int bslot = blockIdx.x, tid = threadIdx.x;
@@ -461,7 +483,9 @@ __global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ p
   }
 
   // ---- 4. inner sweeps ----
-  const int slot = tid / LPS, sub = tid % LPS;
+  // half 0 (threads 0..HT-1) holds columns of R, half 1 columns of W_P in the
+  // split cross pass; elsewhere half 0 works on both and half 1 waits
+  const int half = tid / HT, slot = (tid % HT) / LPS, sub = tid % LPS;
   const int L = max(n1, n2);
   const int nsweeps = mode == 0 ? inner_max : 1;
   int total = 0, sweeps_run = 0;
@@ -470,8 +494,8 @@ __global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ p
     sweeps_run++;
     // (a) within-block pairs, circle round-robin on each block, data in LDS
     if (mode == 0) {
-      const int half = slot >> 4, hs = slot & 15;  // slots 0-15: block 1, 16-31: block 2
-      const int nb = half == 0 ? n1 : n2, base = half == 0 ? 0 : n1;
+      const int blk = slot >> 4, hs = slot & 15;  // slots 0-15: block 1, 16-31: block 2
+      const int nb = blk == 0 ? n1 : n2, base = blk == 0 ? 0 : n1;
       const int nbp = nb + (nb & 1);
       const int rounds = max(n1 + (n1 & 1), n2 + (n2 & 1)) - 1;
       for (int q = 0; q < rounds; q++) {
@@ -482,7 +506,7 @@ __global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ p
           r = min(a, b);
           s = max(a, b);
         }
-        if (r >= 0 && s < nb) {
+        if (half == 0 && r >= 0 && s < nb) {
           T* Rr = R + (base + r) * LDR;
           T* Rs = R + (base + s) * LDR;
           double arr = 0.0, ass = 0.0, are = 0.0, aim = 0.0;
@@ -523,153 +547,242 @@ __global__ __launch_bounds__(32 * LPS) void k_pivot(const double* __restrict__ p
     // use the XOR schedule: in round q slot k meets second-block column
     // k ^ gray(q); from one round to the next a single bit b of gray(q) flips, so
     // every held column moves to slot k ^ 2^b, within the wavefront (DPP or lane
-    // permute) while that slot lies in the same wavefront and through LDS with a
-    // workgroup barrier otherwise (3 of 31 moves for 32 columns).  Other shapes
-    // use the ring: slot k meets column (k + q) mod L, all columns moving one
-    // slot down per round through LDS.
-    if (L > 0 && n2 > 0) {
+    // permute) while that slot lies in the same wavefront and through LDS
+    // otherwise (3 of 31 moves for 32 columns).  There the work is split: the
+    // wavefronts of half 0 hold the columns of R, compute each round's
+    // rotations and publish them; those of half 1 hold the same columns of W_P
+    // and apply the rotations of the previous round, so the W_P updates run
+    // beside the next round's dot products (one barrier per round).  Other
+    // shapes use the ring: slot k meets column (k + q) mod L, all columns
+    // moving one slot down per round through LDS, done by half 0 alone.
+    if (L > 0 && n2 > 0 && n1 == n2 && (L & (L - 1)) == 0) {
+      T* M = half == 0 ? R : W;
+      T a[RPL], b[RPL];
+#pragma unroll
+      for (int i = 0; i < RPL; i++) {
+        const int row = sub + LPS * i;
+        const bool ok = row < m && slot < L;
+        a[i] = ok ? M[slot * LDR + row] : zero_of(T());
+        b[i] = ok ? M[(n1 + slot) * LDR + row] : zero_of(T());
+      }
+      __syncthreads();
+      // LDS exchange buffers (aliasing R and W_P): per half two parities of 32 slots x 64 rows
+      T* ringh = lds + half * (4 * 32 * kMaxPivot / 2);
+      const double sr = slot < L ? (double)sg[slot] : 0.0;
+      double ss = slot < L ? (double)sg[n1 + slot] : 0.0;  // sign of the held second-block column (half 0)
+      for (int q = 0; q <= L; q++) {
+        if (half == 0 && q < L && slot < L) {
+          double arr = 0.0, ass = 0.0, are = 0.0, aim = 0.0;
+#pragma unroll
+          for (int i = 0; i < RPL; i++) {
+            arr += abs2(a[i]);
+            ass += abs2(b[i]);
+            cdot(a[i], b[i], are, aim);
+          }
+          arr = slot_sum<LPS>(arr);
+          ass = slot_sum<LPS>(ass);
+          are = slot_sum<LPS>(are);
+          if (CPLX) aim = slot_sum<LPS>(aim);
+          const double sigma = sr * ss;
+          double cs, sn, pr, pi;
+          const int rc = pair_rotation(arr, ass, are, aim, CPLX, sigma, tol, &cs, &sn, &pr, &pi);
+          if (sub == 0) {
+            prm[q & 1][slot][0] = cs;
+            prm[q & 1][slot][1] = sn;
+            prm[q & 1][slot][2] = -sigma * sn;
+            prm[q & 1][slot][3] = pr;
+            prm[q & 1][slot][4] = pi;
+            prc[q & 1][slot] = rc > 0;
+          }
+          if (rc > 0) {
+#pragma unroll
+            for (int i = 0; i < RPL; i++) {
+              const T f = phase_mul(pr, pi, a[i]), g = b[i];
+              a[i] = lin2(cs, f, -sigma * sn, g);
+              b[i] = lin2(sn, f, cs, g);
+            }
+            cnt += (sub == 0);
+          } else if (rc < 0 && sub == 0) {
+            atomicOr(&s_bad, 1);
+          }
+        } else if (half == 1 && q >= 1 && slot < L && prc[(q - 1) & 1][slot]) {
+          const double* pp = prm[(q - 1) & 1][slot];
+          const double cs = pp[0], sn = pp[1], msn = pp[2], pr = pp[3], pi = pp[4];
+#pragma unroll
+          for (int i = 0; i < RPL; i++) {
+            const T u = phase_mul(pr, pi, a[i]), w = b[i];
+            a[i] = lin2(cs, u, msn, w);
+            b[i] = lin2(sn, u, cs, w);
+          }
+        }
+        // move of the held column: half 0 into round q + 1, half 1 into round q
+        const int mq = half == 0 ? q + 1 : q;
+        const int bit = (mq >= 1 && mq < L) ? __builtin_ctz(mq) : -1;
+        const int lx = bit >= 0 ? (LPS << bit) : 0;
+        if (lx == 8) {
+          if (half == 0) ss = xor8_of(ss);
+#pragma unroll
+          for (int i = 0; i < RPL; i++) b[i] = xor8_of(b[i]);
+        } else if (lx > 0 && lx < 64) {
+          const int addr = ((tid & 63) ^ lx) << 2;
+          if (half == 0) ss = bperm_of(ss, addr);
+#pragma unroll
+          for (int i = 0; i < RPL; i++) b[i] = bperm_of(b[i], addr);
+        }
+        double2* ring = reinterpret_cast<double2*>(ringh + (q & 1) * (32 * kMaxPivot));
+        if (lx >= 64) {
+          if (half == 0 && sub == 0) ring_sg[q & 1][slot] = (int)ss;
+          if constexpr (CPLX) {
+#pragma unroll
+            for (int j = 0; j < RPL; j++) ring[(j * 32 + slot) * LPS + sub] = b[j];
+          } else {
+#pragma unroll
+            for (int j = 0; j < RPL / 2; j++) ring[(j * 32 + slot) * LPS + sub] = double2{b[2 * j], b[2 * j + 1]};
+          }
+        }
+        __syncthreads();
+        if (lx >= 64) {
+          const int from = slot ^ (1 << bit);
+          if (half == 0) ss = (double)ring_sg[q & 1][from];
+          if constexpr (CPLX) {
+#pragma unroll
+            for (int j = 0; j < RPL; j++) b[j] = ring[(j * 32 + from) * LPS + sub];
+          } else {
+#pragma unroll
+            for (int j = 0; j < RPL / 2; j++) {
+              const double2 v = ring[(j * 32 + from) * LPS + sub];
+              b[2 * j] = v.x;
+              b[2 * j + 1] = v.y;
+            }
+          }
+        }
+      }
+      __syncthreads();
+      // write the columns back: slot k holds second-block column k ^ gray(L - 1) = k ^ (L / 2)
+      const int sfin = slot ^ (L >> 1);
+      if (slot < L) {
+#pragma unroll
+        for (int i = 0; i < RPL; i++) {
+          const int row = sub + LPS * i;
+          if (row < m) {
+            M[slot * LDR + row] = a[i];
+            M[(n1 + sfin) * LDR + row] = b[i];
+          }
+        }
+      }
+    } else if (L > 0 && n2 > 0) {
+      // ring schedule, half 0 only (half 1 takes part in the barriers)
       T rr[RPL], wr[RPL], rs[RPL], ws[RPL];
-      const bool have_r = slot < n1;
+      const bool act = half == 0;
+      const bool have_r = act && slot < n1;
 #pragma unroll
       for (int i = 0; i < RPL; i++) {
         const int row = sub + LPS * i;
         const bool ok = row < m;
         rr[i] = (have_r && ok) ? R[slot * LDR + row] : zero_of(T());
         wr[i] = (have_r && ok) ? W[slot * LDR + row] : zero_of(T());
-        rs[i] = (slot < n2 && ok) ? R[(n1 + slot) * LDR + row] : zero_of(T());
-        ws[i] = (slot < n2 && ok) ? W[(n1 + slot) * LDR + row] : zero_of(T());
+        rs[i] = (act && slot < n2 && ok) ? R[(n1 + slot) * LDR + row] : zero_of(T());
+        ws[i] = (act && slot < n2 && ok) ? W[(n1 + slot) * LDR + row] : zero_of(T());
       }
       __syncthreads();
       T* ring0 = lds;
       T* ring1 = lds + 2 * 32 * kMaxPivot;  // each ring: 2 x 32 slots x 64 rows of T
       const double sr = have_r ? (double)sg[slot] : 0.0;
-      double ss = slot < n2 ? (double)sg[n1 + slot] : 0.0;  // sign of the held second-block column
-      // rotate the held pair (first-block column `slot`, held second-block column)
-      auto rotate_held = [&]() {
-        double arr = 0.0, ass = 0.0, are = 0.0, aim = 0.0;
-#pragma unroll
-        for (int i = 0; i < RPL; i++) {
-          arr += abs2(rr[i]);
-          ass += abs2(rs[i]);
-          cdot(rr[i], rs[i], are, aim);
-        }
-        arr = slot_sum<LPS>(arr);
-        ass = slot_sum<LPS>(ass);
-        are = slot_sum<LPS>(are);
-        if (CPLX) aim = slot_sum<LPS>(aim);
-        const double sigma = sr * ss;
-        double cs, sn, pr, pi;
-        const int rc = pair_rotation(arr, ass, are, aim, CPLX, sigma, tol, &cs, &sn, &pr, &pi);
-        if (rc > 0) {
+      double ss = (act && slot < n2) ? (double)sg[n1 + slot] : 0.0;
+      for (int q = 0; q < L; q++) {
+        int sidx = slot + q;  // second-block column held by this slot: (slot + q) mod L
+        if (sidx >= L) sidx -= L;
+        if (act && slot < L && have_r && sidx < n2) {
+          double arr = 0.0, ass = 0.0, are = 0.0, aim = 0.0;
 #pragma unroll
           for (int i = 0; i < RPL; i++) {
-            T f = phase_mul(pr, pi, rr[i]), g = rs[i];
-            rr[i] = lin2(cs, f, -sigma * sn, g);
-            rs[i] = lin2(sn, f, cs, g);
-            T u = phase_mul(pr, pi, wr[i]), w = ws[i];
-            wr[i] = lin2(cs, u, -sigma * sn, w);
-            ws[i] = lin2(sn, u, cs, w);
+            arr += abs2(rr[i]);
+            ass += abs2(rs[i]);
+            cdot(rr[i], rs[i], are, aim);
           }
-          cnt += (sub == 0);
-        } else if (rc < 0 && sub == 0) {
-          atomicOr(&s_bad, 1);
-        }
-      };
-      // publish the held column of every slot in `ring` (16-byte elements: two
-      // reals or one complex, so each lane moves its share with 128-bit LDS
-      // accesses) and take over the one of slot `from`, around a barrier
-      auto exchange_lds = [&](T* ringT, int* rsg, int from) {
-        double2* ring = reinterpret_cast<double2*>(ringT);
-        if (sub == 0) rsg[slot] = (int)ss;
-        if constexpr (CPLX) {
+          arr = slot_sum<LPS>(arr);
+          ass = slot_sum<LPS>(ass);
+          are = slot_sum<LPS>(are);
+          if (CPLX) aim = slot_sum<LPS>(aim);
+          const double sigma = sr * ss;
+          double cs, sn, pr, pi;
+          const int rc = pair_rotation(arr, ass, are, aim, CPLX, sigma, tol, &cs, &sn, &pr, &pi);
+          if (rc > 0) {
 #pragma unroll
-          for (int j = 0; j < RPL; j++) {
-            ring[(j * 32 + slot) * LPS + sub] = rs[j];
-            ring[((RPL + j) * 32 + slot) * LPS + sub] = ws[j];
-          }
-        } else {
-#pragma unroll
-          for (int j = 0; j < RPL / 2; j++) {
-            ring[(j * 32 + slot) * LPS + sub] = double2{rs[2 * j], rs[2 * j + 1]};
-            ring[((RPL / 2 + j) * 32 + slot) * LPS + sub] = double2{ws[2 * j], ws[2 * j + 1]};
+            for (int i = 0; i < RPL; i++) {
+              T f = phase_mul(pr, pi, rr[i]), g = rs[i];
+              rr[i] = lin2(cs, f, -sigma * sn, g);
+              rs[i] = lin2(sn, f, cs, g);
+              T u = phase_mul(pr, pi, wr[i]), w = ws[i];
+              wr[i] = lin2(cs, u, -sigma * sn, w);
+              ws[i] = lin2(sn, u, cs, w);
+            }
+            cnt += (sub == 0);
+          } else if (rc < 0 && sub == 0) {
+            atomicOr(&s_bad, 1);
           }
         }
-        __syncthreads();
-        ss = (double)rsg[from];
-        if constexpr (CPLX) {
+        if (q + 1 < L) {
+          // slot k receives the second-block column of slot (k + 1) mod L; the
+          // ring holds 16-byte elements (two reals or one complex)
+          double2* ring = reinterpret_cast<double2*>((q & 1) ? ring1 : ring0);
+          const int from = slot + 1 < L ? slot + 1 : 0;
+          const bool mv = act && slot < L;
+          if (mv) {
+            if (sub == 0) ring_sg[q & 1][slot] = (int)ss;
+            if constexpr (CPLX) {
 #pragma unroll
-          for (int j = 0; j < RPL; j++) {
-            rs[j] = ring[(j * 32 + from) * LPS + sub];
-            ws[j] = ring[((RPL + j) * 32 + from) * LPS + sub];
-          }
-        } else {
-#pragma unroll
-          for (int j = 0; j < RPL / 2; j++) {
-            const double2 a = ring[(j * 32 + from) * LPS + sub];
-            const double2 b = ring[((RPL / 2 + j) * 32 + from) * LPS + sub];
-            rs[2 * j] = a.x;
-            rs[2 * j + 1] = a.y;
-            ws[2 * j] = b.x;
-            ws[2 * j + 1] = b.y;
-          }
-        }
-      };
-      int sfin;  // second-block column held by this slot after the last round
-      if (n1 == n2 && (L & (L - 1)) == 0) {
-        int nx = 0;  // LDS exchanges so far (alternate buffers)
-        for (int q = 0; q < L; q++) {
-          if (slot < L) rotate_held();
-          if (q + 1 < L) {
-            const int b = __builtin_ctz(q + 1);
-            const int lx = LPS << b;  // lane distance to the partner slot
-            if (lx == 8) {
-              ss = xor8_of(ss);
-#pragma unroll
-              for (int i = 0; i < RPL; i++) {
-                rs[i] = xor8_of(rs[i]);
-                ws[i] = xor8_of(ws[i]);
-              }
-            } else if (lx < 64) {
-              const int addr = ((tid & 63) ^ lx) << 2;
-              ss = bperm_of(ss, addr);
-#pragma unroll
-              for (int i = 0; i < RPL; i++) {
-                rs[i] = bperm_of(rs[i], addr);
-                ws[i] = bperm_of(ws[i], addr);
+              for (int j = 0; j < RPL; j++) {
+                ring[(j * 32 + slot) * LPS + sub] = rs[j];
+                ring[((RPL + j) * 32 + slot) * LPS + sub] = ws[j];
               }
             } else {
-              exchange_lds((nx & 1) ? ring1 : ring0, ring_sg[nx & 1], slot ^ (1 << b));
-              nx++;
+#pragma unroll
+              for (int j = 0; j < RPL / 2; j++) {
+                ring[(j * 32 + slot) * LPS + sub] = double2{rs[2 * j], rs[2 * j + 1]};
+                ring[((RPL / 2 + j) * 32 + slot) * LPS + sub] = double2{ws[2 * j], ws[2 * j + 1]};
+              }
+            }
+          }
+          __syncthreads();
+          if (mv) {
+            ss = (double)ring_sg[q & 1][from];
+            if constexpr (CPLX) {
+#pragma unroll
+              for (int j = 0; j < RPL; j++) {
+                rs[j] = ring[(j * 32 + from) * LPS + sub];
+                ws[j] = ring[((RPL + j) * 32 + from) * LPS + sub];
+              }
+            } else {
+#pragma unroll
+              for (int j = 0; j < RPL / 2; j++) {
+                const double2 u = ring[(j * 32 + from) * LPS + sub];
+                const double2 v = ring[((RPL / 2 + j) * 32 + from) * LPS + sub];
+                rs[2 * j] = u.x;
+                rs[2 * j + 1] = u.y;
+                ws[2 * j] = v.x;
+                ws[2 * j + 1] = v.y;
+              }
             }
           }
         }
-        sfin = slot ^ (L >> 1);  // gray(L - 1) = L / 2
-      } else {
-        for (int q = 0; q < L; q++) {
-          int sidx = slot + q;  // second-block column held by this slot: (slot + q) mod L
-          if (sidx >= L) sidx -= L;
-          if (slot < L && have_r && sidx < n2) rotate_held();
-          if (q + 1 < L) {
-            // slot k receives the second-block column of slot (k + 1) mod L
-            const int from = slot + 1 < L ? slot + 1 : 0;
-            exchange_lds((q & 1) ? ring1 : ring0, ring_sg[q & 1], slot < L ? from : slot);
-          }
-        }
-        sfin = (slot + L - 1) % L;
       }
       __syncthreads();
-      // write the columns back
+      // write the columns back: slot k holds second-block column (k + L - 1) mod L
+      const int sfin = (slot + L - 1) % L;
+      if (act) {
 #pragma unroll
-      for (int i = 0; i < RPL; i++) {
-        const int row = sub + LPS * i;
-        if (row < m) {
-          if (have_r) {
-            R[slot * LDR + row] = rr[i];
-            W[slot * LDR + row] = wr[i];
-          }
-          if (slot < L && sfin < n2) {
-            R[(n1 + sfin) * LDR + row] = rs[i];
-            W[(n1 + sfin) * LDR + row] = ws[i];
+        for (int i = 0; i < RPL; i++) {
+          const int row = sub + LPS * i;
+          if (row < m) {
+            if (have_r) {
+              R[slot * LDR + row] = rr[i];
+              W[slot * LDR + row] = wr[i];
+            }
+            if (slot < L && sfin < n2) {
+              R[(n1 + sfin) * LDR + row] = rs[i];
+              W[(n1 + sfin) * LDR + row] = ws[i];
+            }
           }
         }
       }
@@ -712,14 +825,14 @@ constexpr int kPivotLPS = 8;
 void launch_pivot_f64(const double* part, int nch, int n, int rows_per_chunk, const PivotList& pl, double tol,
                       int inner_max, int inner_mode, int soft, double* W, int* rotflag, SweepStats* st,
                       hipStream_t stream, const Batch& b) {
-  launch((k_pivot<false, kPivotLPS>), dim3(pl.count), dim3(32 * kPivotLPS), 0, stream, part, nch, n,
+  launch((k_pivot<false, kPivotLPS>), dim3(pl.count), dim3(64 * kPivotLPS), 0, stream, part, nch, n,
                      rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st, b);
 }
 
 void launch_pivot_c128(const double* part, int nch, int n, int rows_per_chunk, const PivotList& pl, double tol,
                        int inner_max, int inner_mode, int soft, double* W, int* rotflag, SweepStats* st,
                        hipStream_t stream, const Batch& b) {
-  launch((k_pivot<true, kPivotLPS>), dim3(pl.count), dim3(32 * kPivotLPS), 0, stream, part, nch, n,
+  launch((k_pivot<true, kPivotLPS>), dim3(pl.count), dim3(64 * kPivotLPS), 0, stream, part, nch, n,
                      rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st, b);
 }
 
