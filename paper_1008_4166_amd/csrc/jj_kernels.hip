@@ -26,17 +26,23 @@ __device__ __forceinline__ void atomic_max_nonneg(unsigned long long* addr, doub
 }
 
 // ---------------------------------------------------------------------------
-// Gram partials.  Grid (nch, P), 256 threads.  Chunk ch covers rows
-// [ch*rows_per_chunk, min(n, (ch+1)*rows_per_chunk)).  Each wave takes 16-row
-// groups; within a group lane l (column c16 = l%16 of each 16-column tile,
-// row quarter g = l/16) holds rows 4g..4g+3, so the four k-steps of the group
-// are rows {4g + kk}.  All upper tiles (I <= J) of the 64x64 partial are
-// accumulated; the four waves are reduced through LDS in a fixed order.
+// Gram partials.  Grid (chunks, P), 256 threads.  Chunk ch covers rows
+// [ch*rows_per_chunk, min(n, (ch+1)*rows_per_chunk)).  The chunk is staged
+// through LDS in blocks of 64 rows: each wave loads whole columns (lane = row,
+// 512 contiguous bytes per instruction) into a column-major LDS block with
+// column stride 68, while the previous block is multiplied; the MFMA operands
+// are then read from LDS (lane (c16, g) takes row 4kk + g of column 16T + c16,
+// word offset 8 c16 + 2g modulo the 64 banks).  Wave w accumulates all 10 upper
+// 16x16 tiles over rows 16w..16w+15 of every block; the four waves are reduced
+// through LDS in a fixed order and the partial is written per chunk.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256, 3) void k_gram_f64(const double* __restrict__ G0, int ldg0, int n0,
-                                                  const int* __restrict__ cols, const int* __restrict__ mlist,
-                                                  int rows_per_chunk, double* __restrict__ part, Batch bt) {
-  __shared__ d4 red[2][10][64];
+constexpr int kGramRows = 64;
+constexpr int kGramLdc = 68;
+
+__global__ __launch_bounds__(256, 2) void k_gram_f64(const double* __restrict__ G0, int ldg0, int n0,
+                                                     const int* __restrict__ cols, const int* __restrict__ mlist,
+                                                     int rows_per_chunk, double* __restrict__ part, Batch bt) {
+  __shared__ double smem[2 * kMaxPivot * kGramLdc];  // two staged blocks; then the wave reduction
   const int nch = gridDim.x;
   int slot, ch;
   xcd_slot_chunk(slot, ch);
@@ -49,66 +55,77 @@ __global__ __launch_bounds__(256, 3) void k_gram_f64(const double* __restrict__ 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int c16 = lane & 15, g = lane >> 4;
   const int m = mlist[p];
+  if (m <= 0) return;  // empty pivot (a padding slot): no columns, no partial
   const int nt = (m + 15) >> 4;
   const int r0 = ch * rows_per_chunk;
   const int r1 = min(n, r0 + rows_per_chunk);
+  const int nblk = (r1 - r0 + kGramRows - 1) / kGramRows;
 
-  const gdbl* cp[4];
+  // loader: wave w stages columns w + 4i (i < 16), lane = row of the block;
+  // loads are unconditional (a padding column reads the pivot's first column,
+  // a row past the chunk its last row) and zeroed by a 0/1 factor (the matrix
+  // is finite: non-finite input is rejected before the sweeps)
+  const int c0 = cols[p * kMaxPivot];
+  size_t coff[16];
+  unsigned okbits = 0;
 #pragma unroll
-  for (int J = 0; J < 4; J++) {
-    int c = J * 16 + c16;
-    int pc = (c < m) ? cols[p * kMaxPivot + c] : -1;
-    cp[J] = (pc >= 0) ? G + (size_t)pc * ldg : nullptr;
+  for (int i = 0; i < 16; i++) {
+    const int c = wave + 4 * i;
+    const int pc = c < m ? cols[p * kMaxPivot + c] : -1;
+    okbits |= pc >= 0 ? (1u << i) : 0u;
+    coff[i] = (size_t)(pc >= 0 ? pc : c0) * ldg;
   }
+  double ld[16];
+  auto load_block = [&](int b) {
+    const int row = r0 + b * kGramRows + lane;
+    const unsigned ok = row < r1 ? okbits : 0u;
+    const int rl = min(row, r1 - 1);
+#pragma unroll
+    for (int i = 0; i < 16; i++) ld[i] = G[coff[i] + rl] * ((ok >> i) & 1u ? 1.0 : 0.0);
+  };
+  auto store_block = [&](int buf) {
+    double* S = smem + buf * (kMaxPivot * kGramLdc);
+#pragma unroll
+    for (int i = 0; i < 16; i++) S[(wave + 4 * i) * kGramLdc + lane] = ld[i];
+  };
+
   d4 acc[10];
 #pragma unroll
   for (int t = 0; t < 10; t++) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
-
-  // software pipeline: the loads of the next 16-row group are in flight while
-  // the MFMAs of the current group run
-  double x[4][4], xn[4][4];
-  int base = r0 + wave * 16;
-#pragma unroll
-  for (int J = 0; J < 4; J++)
-#pragma unroll
-    for (int kk = 0; kk < 4; kk++) {
-      int row = base + 4 * g + kk;
-      x[J][kk] = (cp[J] != nullptr && row < r1) ? cp[J][row] : 0.0;
-    }
-  for (; base < r1; base += 64) {
-    const int nb = base + 64;
-#pragma unroll
-    for (int J = 0; J < 4; J++)
-#pragma unroll
-      for (int kk = 0; kk < 4; kk++) {
-        int row = nb + 4 * g + kk;
-        xn[J][kk] = (cp[J] != nullptr && row < r1) ? cp[J][row] : 0.0;
-      }
+  load_block(0);
+  store_block(0);
+  __syncthreads();
+  for (int b = 0; b < nblk; b++) {
+    if (b + 1 < nblk) load_block(b + 1);  // in flight during the MFMAs below
+    const double* S = smem + (b & 1) * (kMaxPivot * kGramLdc);
 #pragma unroll
     for (int kk = 0; kk < 4; kk++) {
+      const int row = 16 * wave + 4 * kk + g;
+      double xt[4];
+#pragma unroll
+      for (int T = 0; T < 4; T++) xt[T] = S[(16 * T + c16) * kGramLdc + row];
       int t = 0;
 #pragma unroll
       for (int I = 0; I < 4; I++)
 #pragma unroll
         for (int J = I; J < 4; J++) {
-          if (J < nt) acc[t] = mfma16(x[I][kk], x[J][kk], acc[t]);
+          if (J < nt) acc[t] = mfma16(xt[I], xt[J], acc[t]);
           t++;
         }
     }
-#pragma unroll
-    for (int J = 0; J < 4; J++)
-#pragma unroll
-      for (int kk = 0; kk < 4; kk++) x[J][kk] = xn[J][kk];
+    if (b + 1 < nblk) store_block((b + 1) & 1);
+    __syncthreads();
   }
-  // fixed-order reduction of the four waves: (w0 + w2) + (w1 + w3)
+  // fixed-order reduction of the four waves: (w0 + w2) + (w1 + w3), through LDS
+  d4* red = reinterpret_cast<d4*>(smem);  // [2][10][64]
   if (wave >= 2)
-    for (int t = 0; t < 10; t++) red[wave - 2][t][lane] = acc[t];
+    for (int t = 0; t < 10; t++) red[((wave - 2) * 10 + t) * 64 + lane] = acc[t];
   __syncthreads();
   if (wave < 2)
-    for (int t = 0; t < 10; t++) acc[t] += red[wave][t][lane];
+    for (int t = 0; t < 10; t++) acc[t] += red[(wave * 10 + t) * 64 + lane];
   __syncthreads();
   if (wave == 1)
-    for (int t = 0; t < 10; t++) red[0][t][lane] = acc[t];
+    for (int t = 0; t < 10; t++) red[t * 64 + lane] = acc[t];
   __syncthreads();
   if (wave == 0) {
     double* out = part + ((size_t)slot * nch + ch) * (kMaxPivot * kMaxPivot);
@@ -117,10 +134,10 @@ __global__ __launch_bounds__(256, 3) void k_gram_f64(const double* __restrict__ 
     for (int I = 0; I < 4; I++)
 #pragma unroll
       for (int J = I; J < 4; J++) {
-        d4 s = acc[t] + red[0][t][lane];
+        const d4 sacc = acc[t] + red[t * 64 + lane];
         if (J < nt) {
 #pragma unroll
-          for (int v = 0; v < 4; v++) out[(16 * I + 4 * v + g) * kMaxPivot + 16 * J + c16] = s[v];
+          for (int v = 0; v < 4; v++) out[(16 * I + 4 * v + g) * kMaxPivot + 16 * J + c16] = sacc[v];
         }
         t++;
       }
@@ -139,7 +156,7 @@ __global__ __launch_bounds__(256, 3) void k_gram_f64(const double* __restrict__ 
 // complex reads too: 16 c16 + 4g).
 constexpr int LDW = kMaxPivot + 4;
 
-__global__ __launch_bounds__(256) void k_update_f64(double* __restrict__ G0, int ldg0, int n0,
+__global__ __launch_bounds__(256, 4) void k_update_f64(double* __restrict__ G0, int ldg0, int n0,
                                                     const int* __restrict__ cols, const int* __restrict__ mlist,
                                                     const double* __restrict__ Wg, const int* __restrict__ rotflag,
                                                     int rows_per_chunk, Batch bt) {
@@ -157,6 +174,7 @@ __global__ __launch_bounds__(256) void k_update_f64(double* __restrict__ G0, int
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int c16 = lane & 15, g = lane >> 4;
   const int m = mlist[p];
+  if (m <= 0) return;             // empty pivot (a padding slot)
   const int nt = (m + 15) >> 4;   // output column tiles
   const int ks = (m + 3) >> 2;    // k-steps of 4 columns
   const double* Wp = Wg + (size_t)slot * (kMaxPivot * kMaxPivot);
@@ -169,23 +187,39 @@ __global__ __launch_bounds__(256) void k_update_f64(double* __restrict__ G0, int
 
   const int r0 = ch * rows_per_chunk;
   const int r1 = min(n, r0 + rows_per_chunk);
-  int pcol[16];
-#pragma unroll
-  for (int kk = 0; kk < 16; kk++) pcol[kk] = scol[4 * kk + g];
-  // the next strip's loads are issued before the current strip's MFMAs
-  double x[16], xn[16];
-  int row0 = r0 + wave * 16;
+  // Loads are unconditional, from clamped addresses (a padding column reads
+  // the pivot's first column, a row past the chunk its last row), and padding
+  // values are zeroed by a 0/1 factor (the matrix is finite: non-finite input
+  // is rejected before the sweeps): no branch around a load, so outstanding
+  // loads are counted instead of drained at every use.
+  size_t coff[16];
+  unsigned okbits = 0;
 #pragma unroll
   for (int kk = 0; kk < 16; kk++) {
+    const int pc = scol[4 * kk + g];
+    const bool ok = kk < ks && pc >= 0;
+    okbits |= ok ? (1u << kk) : 0u;
+    coff[kk] = (size_t)(ok ? pc : scol[0]) * ldg;
+  }
+  // the next strip's loads are issued before the current strip's MFMAs (the
+  // scheduling barrier keeps them there)
+  double x[16], xn[16];
+  int row0 = r0 + wave * 16;
+  {
     const int row = row0 + c16;
-    x[kk] = (kk < ks && pcol[kk] >= 0 && row < r1) ? G[(size_t)pcol[kk] * ldg + row] : 0.0;
+    const unsigned ok = row < r1 ? okbits : 0u;
+    const int rl = min(row, r1 - 1);
+#pragma unroll
+    for (int kk = 0; kk < 16; kk++) x[kk] = G[coff[kk] + rl] * ((ok >> kk) & 1u ? 1.0 : 0.0);
   }
   for (; row0 < r1; row0 += 64) {
     const int row = row0 + c16;
     const int nrow = row + 64;
+    const unsigned nok = nrow < r1 ? okbits : 0u;
+    const int nrl = min(nrow, r1 - 1);
 #pragma unroll
-    for (int kk = 0; kk < 16; kk++)
-      xn[kk] = (kk < ks && pcol[kk] >= 0 && nrow < r1) ? G[(size_t)pcol[kk] * ldg + nrow] : 0.0;
+    for (int kk = 0; kk < 16; kk++) xn[kk] = G[coff[kk] + nrl] * ((nok >> kk) & 1u ? 1.0 : 0.0);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int I = 0; I < 4; I++) {
       if (I < nt) {
