@@ -139,7 +139,11 @@ def cpu_baseline(n_full, sweeps_full):
     r = oracle.solve(G, J, max_sweeps=1, vectors=False)
     dt = time.perf_counter() - t
     t_full = dt * (n_full / ns) ** 3 * sweeps_full
-    return dict(value=n_full / t_full, unit="eigenpairs/s", cores=1, kind="oracle",
+    G1, J1, _ = jjgen.config(1)
+    t1 = time.perf_counter()
+    oracle.solve(G1, J1, vectors=False)
+    dt1 = time.perf_counter() - t1
+    return dict(value=n_full / t_full, unit="eigenpairs/s", cores=1, kind="oracle", workload1_seconds=dt1,
                 sample="one oracle sweep on the n=%d instance of the workload (%.1f s), scaled by (4096/%d)^3 "
                        "and by the oracle's %d sweeps on the n=4096 input" % (ns, dt, ns, sweeps_full),
                 sweep_seconds_sample=dt, status_sample=r["status"])
@@ -236,6 +240,46 @@ def bench_batched(jj, torch, count, loop_sample):
                          "|lambda| log-uniform [1e-6, 1e3]" if count == 4096 else "batch of %d" % count)
 
 
+def bench_small(jj, torch, k, reps):
+    """Workloads 1 (n = 64 real) and 2 (n = 1024 complex, b = 32): median solve
+    time over `reps` solves, sweeps, accuracy against the prescribed spectrum
+    and against the stored oracle eigenvalues where they exist."""
+    import jjgen
+    G, J, lam_pres = jjgen.config(k)
+    n = G.shape[0]
+    cplx = np.iscomplexobj(G)
+    dev = torch.device("cuda:0")
+    pristine = torch.from_numpy(np.ascontiguousarray(G.T)).to(dev)
+    lam = torch.empty(n, dtype=torch.float64, device=dev)
+    Vt = torch.empty((n, n), dtype=pristine.dtype, device=dev)
+    stream = torch.cuda.current_stream().cuda_stream
+    o = jj.make_opts(stream=stream, block_width=32)
+    times = []
+    for r in range(reps + 1):
+        Gw = pristine.clone()
+        info = jj.jj_info()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = jj.jjacobi_solve_ex(jj.JJ_C128 if cplx else jj.JJ_F64, Gw.data_ptr(), J, n, n, lam.data_ptr(),
+                                 Vt.data_ptr(), n, 0.0, 0, o, info)
+        torch.cuda.synchronize()
+        if st != 0:
+            raise RuntimeError("workload %d solve status %d" % (k, st))
+        if r > 0:  # the first solve is a warm-up
+            times.append(time.perf_counter() - t0)
+    lh = lam.cpu().numpy()
+    ref = np.sort(lam_pres)[::-1]
+    out = dict(n=n, dtype="complex128" if cplx else "float64", seconds_median=float(np.median(times)),
+               eigenpairs_per_s=n / float(np.median(times)), sweeps=info.sweeps,
+               ms_per_sweep=1e3 * float(np.median(times)) / max(1, info.sweeps),
+               vs_prescribed_max_rel=float(np.max(np.abs(lh - ref) / np.abs(ref))))
+    ora, osw = stored_oracle(k)
+    if ora is not None:
+        out["vs_oracle_max_rel"] = float(np.max(np.abs(lh - ora) / np.abs(ora)))
+        out["oracle_sweeps"] = osw
+    return out
+
+
 def bench_config4(jj, torch, steps):
     """n = 8192 complex Hermitian workload (p = 4096, |lambda| log-uniform in
     [1e-8, 1e2]): plain complex128 solves against the mixed form (FP32-MFMA
@@ -320,6 +364,7 @@ def main():
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--loop-sample", type=int, default=64)
     ap.add_argument("--no-c4", action="store_true", help="skip the n=8192 complex leg")
+    ap.add_argument("--no-small", action="store_true", help="skip the n=64 and n=1024 legs")
     ap.add_argument("--c4-steps", type=int, default=1)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="before the timed region, one device copy of this many MiB (a reference for "
@@ -451,6 +496,10 @@ def main():
         out["mixed"] = dict(value=n * K / dtm, ms_per_step=dtm / K * 1e3, sweeps=[i["sweeps"] for i in minfos],
                             mixed_sweeps=[i["mixed_sweeps"] for i in minfos], accuracy=macc,
                             speedup_vs_fp64=ms_step / (dtm / K * 1e3))
+    if not args.no_small:
+        note("workloads 1 and 2")
+        out["config1"] = bench_small(jj, torch, 1, 20)
+        out["config2"] = bench_small(jj, torch, 2, 5)
     if not args.no_batched:
         note("batched leg")
         out["batched"] = bench_batched(jj, torch, args.batch_count, args.loop_sample)
