@@ -244,10 +244,18 @@ __global__ __launch_bounds__(256, 4) void k_update_f64(double* __restrict__ G0, 
 // Complex Hermitian (complex128, interleaved).  A = X^H X is formed from real
 // MFMA products: Re A = Xr^T Xr + Xi^T Xi, Im A = Xr^T Xi - Xi^T Xr.
 // ---------------------------------------------------------------------------
+// Complex Gram: the same staging with 32-row blocks of (re, im) pairs (512
+// contiguous bytes per column and block, two columns per wave instruction),
+// column stride 36 pairs in LDS (16-byte operand reads spread over the banks:
+// 16 c16 + 4g words); Re A = Xr^T Xr + Xi^T Xi, Im A = Xr^T Xi - Xi^T Xr on
+// FP64 MFMA; waves reduced in the order ((w3 + w2) + w1) + w0.
+constexpr int kGramRowsC = 32;
+constexpr int kGramLdcC = 36;
+
 __global__ __launch_bounds__(256, 2) void k_gram_c128(const double* __restrict__ G0, int ldg0, int n0,
-                                                   const int* __restrict__ cols, const int* __restrict__ mlist,
-                                                   int rows_per_chunk, double* __restrict__ part, Batch bt) {
-  __shared__ d4 red[10][2][64];
+                                                     const int* __restrict__ cols, const int* __restrict__ mlist,
+                                                     int rows_per_chunk, double* __restrict__ part, Batch bt) {
+  __shared__ dv2 smem[2 * kMaxPivot * kGramLdcC];  // two staged blocks; then the wave reduction
   const int nch = gridDim.x;
   int slot, ch;
   xcd_slot_chunk(slot, ch);
@@ -260,32 +268,60 @@ __global__ __launch_bounds__(256, 2) void k_gram_c128(const double* __restrict__
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int c16 = lane & 15, g = lane >> 4;
   const int m = mlist[p];
+  if (m <= 0) return;  // empty pivot (a padding slot)
   const int nt = (m + 15) >> 4;
   const int r0 = ch * rows_per_chunk;
   const int r1 = min(n, r0 + rows_per_chunk);
-  const gdbl2* cp[4];
+  const int nblk = (r1 - r0 + kGramRowsC - 1) / kGramRowsC;
+
+  // loader: wave w, instruction i stages column 2 (w + 4i) + lane / 32, row lane % 32;
+  // unconditional clamped loads, padding zeroed by a 0/1 factor (finite matrix)
+  const int c0 = cols[p * kMaxPivot];
+  const int lrow = lane & 31, lcol = lane >> 5;
+  size_t coff[8];
+  unsigned okbits = 0;
 #pragma unroll
-  for (int J = 0; J < 4; J++) {
-    int c = J * 16 + c16;
-    int pc = (c < m) ? cols[p * kMaxPivot + c] : -1;
-    cp[J] = (pc >= 0) ? G + (size_t)pc * ldg : nullptr;
+  for (int i = 0; i < 8; i++) {
+    const int c = 2 * (wave + 4 * i) + lcol;
+    const int pc = c < m ? cols[p * kMaxPivot + c] : -1;
+    okbits |= pc >= 0 ? (1u << i) : 0u;
+    coff[i] = (size_t)(pc >= 0 ? pc : c0) * ldg;
   }
+  dv2 ld[8];
+  auto load_block = [&](int b) {
+    const int row = r0 + b * kGramRowsC + lrow;
+    const unsigned ok = row < r1 ? okbits : 0u;
+    const int rl = min(row, r1 - 1);
+#pragma unroll
+    for (int i = 0; i < 8; i++) ld[i] = G[coff[i] + rl] * ((ok >> i) & 1u ? 1.0 : 0.0);
+  };
+  auto store_block = [&](int buf) {
+    dv2* S = smem + buf * (kMaxPivot * kGramLdcC);
+#pragma unroll
+    for (int i = 0; i < 8; i++) S[(2 * (wave + 4 * i) + lcol) * kGramLdcC + lrow] = ld[i];
+  };
+
   d4 are[10], aim[10];
 #pragma unroll
   for (int t = 0; t < 10; t++) {
     are[t] = d4{0.0, 0.0, 0.0, 0.0};
     aim[t] = d4{0.0, 0.0, 0.0, 0.0};
   }
-  for (int base = r0 + wave * 16; base < r1; base += 64) {
+  load_block(0);
+  store_block(0);
+  __syncthreads();
+  for (int b = 0; b < nblk; b++) {
+    if (b + 1 < nblk) load_block(b + 1);  // in flight during the MFMAs below
+    const dv2* S = smem + (b & 1) * (kMaxPivot * kGramLdcC);
 #pragma unroll
-    for (int kk = 0; kk < 4; kk++) {
-      const int row = base + 4 * g + kk;
+    for (int kk = 0; kk < 2; kk++) {
+      const int row = 8 * wave + 4 * kk + g;
       double xr[4], xi[4];
 #pragma unroll
-      for (int J = 0; J < 4; J++) {
-        const dv2 v = (cp[J] != nullptr && row < r1) ? cp[J][row] : dv2{0.0, 0.0};
-        xr[J] = v.x;
-        xi[J] = v.y;
+      for (int T = 0; T < 4; T++) {
+        const dv2 v = S[(16 * T + c16) * kGramLdcC + row];
+        xr[T] = v.x;
+        xi[T] = v.y;
       }
       int t = 0;
 #pragma unroll
@@ -301,19 +337,22 @@ __global__ __launch_bounds__(256, 2) void k_gram_c128(const double* __restrict__
           t++;
         }
     }
+    if (b + 1 < nblk) store_block((b + 1) & 1);
+    __syncthreads();
   }
-  // fixed-order reduction: ((w3 + w2) + w1) + w0
+  // fixed-order reduction: ((w3 + w2) + w1) + w0, through LDS
+  d4* red = reinterpret_cast<d4*>(smem);  // [10][2][64]
   for (int w = 3; w >= 1; w--) {
     if (wave == w)
       for (int t = 0; t < 10; t++) {
-        red[t][0][lane] = are[t];
-        red[t][1][lane] = aim[t];
+        red[(t * 2 + 0) * 64 + lane] = are[t];
+        red[(t * 2 + 1) * 64 + lane] = aim[t];
       }
     __syncthreads();
     if (wave == w - 1)
       for (int t = 0; t < 10; t++) {
-        are[t] = red[t][0][lane] + are[t];
-        aim[t] = red[t][1][lane] + aim[t];
+        are[t] = red[(t * 2 + 0) * 64 + lane] + are[t];
+        aim[t] = red[(t * 2 + 1) * 64 + lane] + aim[t];
       }
     __syncthreads();
   }
