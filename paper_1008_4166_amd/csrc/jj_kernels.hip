@@ -407,23 +407,34 @@ __global__ __launch_bounds__(256, 2) void k_update_c128(double* __restrict__ G0,
   gdbl2* Gc = as_global2(Gm);
   const int r0 = ch * rows_per_chunk;
   const int r1 = min(n, r0 + rows_per_chunk);
-  int pcol[16];
+  // unconditional loads from clamped addresses, padding zeroed by a 0/1
+  // factor (finite matrix): outstanding loads are counted, not drained
+  size_t coff[16];
+  unsigned okbits = 0;
 #pragma unroll
-  for (int kk = 0; kk < 16; kk++) pcol[kk] = scol[4 * kk + g];
+  for (int kk = 0; kk < 16; kk++) {
+    const int pc = scol[4 * kk + g];
+    const bool ok = kk < ks && pc >= 0;
+    okbits |= ok ? (1u << kk) : 0u;
+    coff[kk] = (size_t)(ok ? pc : scol[0]) * ldg;
+  }
   // the next strip's loads are issued before the current strip's MFMAs
   dv2 x[16], xn[16];
   int row0 = r0 + wave * 16;
-#pragma unroll
-  for (int kk = 0; kk < 16; kk++) {
+  {
     const int row = row0 + c16;
-    x[kk] = (kk < ks && pcol[kk] >= 0 && row < r1) ? Gc[(size_t)pcol[kk] * ldg + row] : dv2{0.0, 0.0};
+    const unsigned ok = row < r1 ? okbits : 0u;
+    const int rl = min(row, r1 - 1);
+#pragma unroll
+    for (int kk = 0; kk < 16; kk++) x[kk] = Gc[coff[kk] + rl] * ((ok >> kk) & 1u ? 1.0 : 0.0);
   }
   for (; row0 < r1; row0 += 64) {
     const int row = row0 + c16;
     const int nrow = row + 64;
+    const unsigned nok = nrow < r1 ? okbits : 0u;
+    const int nrl = min(nrow, r1 - 1);
 #pragma unroll
-    for (int kk = 0; kk < 16; kk++)
-      xn[kk] = (kk < ks && pcol[kk] >= 0 && nrow < r1) ? Gc[(size_t)pcol[kk] * ldg + nrow] : dv2{0.0, 0.0};
+    for (int kk = 0; kk < 16; kk++) xn[kk] = Gc[coff[kk] + nrl] * ((nok >> kk) & 1u ? 1.0 : 0.0);
     // three real products per complex one (Gauss): T1 = Xr Wr, T2 = Xi Wi,
     // T3 = (Xr + Xi)(Wr + Wi); Re = T1 - T2, Im = T3 - T1 - T2 (transposed here)
 #pragma unroll
