@@ -13,6 +13,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 namespace jj {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -95,27 +97,35 @@ __global__ __launch_bounds__(256, 2) void k_gram_f64(const double* __restrict__ 
   load_block(0);
   store_block(0);
   __syncthreads();
-  for (int b = 0; b < nblk; b++) {
-    if (b + 1 < nblk) load_block(b + 1);  // in flight during the MFMAs below
-    const double* S = smem + (b & 1) * (kMaxPivot * kGramLdc);
+  // full: all four column tiles in use (m > 48), the tile loop has no branch
+  // (a branch around each MFMA would serialise them)
+  auto rows = [&](auto full) {
+    for (int b = 0; b < nblk; b++) {
+      if (b + 1 < nblk) load_block(b + 1);  // in flight during the MFMAs below
+      const double* S = smem + (b & 1) * (kMaxPivot * kGramLdc);
 #pragma unroll
-    for (int kk = 0; kk < 4; kk++) {
-      const int row = 16 * wave + 4 * kk + g;
-      double xt[4];
+      for (int kk = 0; kk < 4; kk++) {
+        const int row = 16 * wave + 4 * kk + g;
+        double xt[4];
 #pragma unroll
-      for (int T = 0; T < 4; T++) xt[T] = S[(16 * T + c16) * kGramLdc + row];
-      int t = 0;
+        for (int T = 0; T < 4; T++) xt[T] = S[(16 * T + c16) * kGramLdc + row];
+        int t = 0;
 #pragma unroll
-      for (int I = 0; I < 4; I++)
+        for (int I = 0; I < 4; I++)
 #pragma unroll
-        for (int J = I; J < 4; J++) {
-          if (J < nt) acc[t] = mfma16(xt[I], xt[J], acc[t]);
-          t++;
-        }
+          for (int J = I; J < 4; J++) {
+            if (decltype(full)::value || J < nt) acc[t] = mfma16(xt[I], xt[J], acc[t]);
+            t++;
+          }
+      }
+      if (b + 1 < nblk) store_block((b + 1) & 1);
+      __syncthreads();
     }
-    if (b + 1 < nblk) store_block((b + 1) & 1);
-    __syncthreads();
-  }
+  };
+  if (nt == 4)
+    rows(std::true_type{});
+  else
+    rows(std::false_type{});
   // fixed-order reduction of the four waves: (w0 + w2) + (w1 + w3), through LDS
   d4* red = reinterpret_cast<d4*>(smem);  // [2][10][64]
   if (wave >= 2)
@@ -171,6 +181,7 @@ __global__ __launch_bounds__(256, 4) void k_update_f64(double* __restrict__ G0, 
   gdbl* G = as_global(Gm);
   __shared__ double Ws[kMaxPivot * LDW];
   __shared__ int scol[kMaxPivot];
+  __shared__ size_t soff[kMaxPivot];  // clamped element offsets of the pivot's columns
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int c16 = lane & 15, g = lane >> 4;
   const int m = mlist[p];
@@ -182,7 +193,11 @@ __global__ __launch_bounds__(256, 4) void k_update_f64(double* __restrict__ G0, 
     int c = e >> 6, r = e & 63;
     Ws[c * LDW + r] = (r < m && c < m) ? Wp[c * kMaxPivot + r] : 0.0;
   }
-  if (tid < kMaxPivot) scol[tid] = (tid < m) ? cols[p * kMaxPivot + tid] : -1;
+  if (tid < kMaxPivot) {
+    const int pc = (tid < m) ? cols[p * kMaxPivot + tid] : -1;
+    scol[tid] = pc;
+    soff[tid] = (size_t)(pc >= 0 ? pc : cols[p * kMaxPivot]) * ldg;
+  }
   __syncthreads();
 
   const int r0 = ch * rows_per_chunk;
@@ -192,15 +207,11 @@ __global__ __launch_bounds__(256, 4) void k_update_f64(double* __restrict__ G0, 
   // values are zeroed by a 0/1 factor (the matrix is finite: non-finite input
   // is rejected before the sweeps): no branch around a load, so outstanding
   // loads are counted instead of drained at every use.
-  size_t coff[16];
+  // (the offsets are read from LDS at each load, which keeps four wavefronts
+  // per SIMD within the register budget)
   unsigned okbits = 0;
 #pragma unroll
-  for (int kk = 0; kk < 16; kk++) {
-    const int pc = scol[4 * kk + g];
-    const bool ok = kk < ks && pc >= 0;
-    okbits |= ok ? (1u << kk) : 0u;
-    coff[kk] = (size_t)(ok ? pc : scol[0]) * ldg;
-  }
+  for (int kk = 0; kk < 16; kk++) okbits |= (kk < ks && 4 * kk + g < m) ? (1u << kk) : 0u;
   // the next strip's loads are issued before the current strip's MFMAs (the
   // scheduling barrier keeps them there)
   double x[16], xn[16];
@@ -210,34 +221,48 @@ __global__ __launch_bounds__(256, 4) void k_update_f64(double* __restrict__ G0, 
     const unsigned ok = row < r1 ? okbits : 0u;
     const int rl = min(row, r1 - 1);
 #pragma unroll
-    for (int kk = 0; kk < 16; kk++) x[kk] = G[coff[kk] + rl] * ((ok >> kk) & 1u ? 1.0 : 0.0);
+    for (int kk = 0; kk < 16; kk++) x[kk] = G[soff[4 * kk + g] + rl] * ((ok >> kk) & 1u ? 1.0 : 0.0);
   }
-  for (; row0 < r1; row0 += 64) {
-    const int row = row0 + c16;
-    const int nrow = row + 64;
-    const unsigned nok = nrow < r1 ? okbits : 0u;
-    const int nrl = min(nrow, r1 - 1);
+  // full: a 64-column pivot; the MFMA loops have no branch (a branch around
+  // each MFMA would serialise them) and the four output tiles accumulate side
+  // by side.  Otherwise tiles and k-steps beyond m are skipped.
+  auto rows = [&](auto full) {
+    for (; row0 < r1; row0 += 64) {
+      const int row = row0 + c16;
+      const int nrow = row + 64;
+      const unsigned nok = nrow < r1 ? okbits : 0u;
+      const int nrl = min(nrow, r1 - 1);
 #pragma unroll
-    for (int kk = 0; kk < 16; kk++) xn[kk] = G[coff[kk] + nrl] * ((nok >> kk) & 1u ? 1.0 : 0.0);
-    __builtin_amdgcn_sched_barrier(0);
+      for (int kk = 0; kk < 16; kk++) xn[kk] = G[soff[4 * kk + g] + nrl] * ((nok >> kk) & 1u ? 1.0 : 0.0);
+      __builtin_amdgcn_sched_barrier(0);
+      d4 acc[4];
 #pragma unroll
-    for (int I = 0; I < 4; I++) {
-      if (I < nt) {
-        d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+      for (int I = 0; I < 4; I++) acc[I] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int kk = 0; kk < 16; kk++)
-          if (kk < ks) acc = mfma16(Ws[(16 * I + c16) * LDW + 4 * kk + g], x[kk], acc);
+      for (int kk = 0; kk < 16; kk++)
 #pragma unroll
-        for (int v = 0; v < 4; v++) {
-          int oc = 16 * I + 4 * v + g;
-          int pc = scol[oc];
-          if (oc < m && row < r1) G[(size_t)pc * ldg + row] = acc[v];
+        for (int I = 0; I < 4; I++)
+          if (decltype(full)::value || (I < nt && kk < ks))
+            acc[I] = mfma16(Ws[(16 * I + c16) * LDW + 4 * kk + g], x[kk], acc[I]);
+#pragma unroll
+      for (int I = 0; I < 4; I++) {
+        if (decltype(full)::value || I < nt) {
+#pragma unroll
+          for (int v = 0; v < 4; v++) {
+            int oc = 16 * I + 4 * v + g;
+            int pc = scol[oc];
+            if (oc < m && row < r1) G[(size_t)pc * ldg + row] = acc[I][v];
+          }
         }
       }
-    }
 #pragma unroll
-    for (int kk = 0; kk < 16; kk++) x[kk] = xn[kk];
-  }
+      for (int kk = 0; kk < 16; kk++) x[kk] = xn[kk];
+    }
+  };
+  if (m == kMaxPivot)
+    rows(std::true_type{});
+  else
+    rows(std::false_type{});
 }
 
 // ---------------------------------------------------------------------------
@@ -247,10 +272,50 @@ __global__ __launch_bounds__(256, 4) void k_update_f64(double* __restrict__ G0, 
 // Complex Gram: the same staging with 32-row blocks of (re, im) pairs (512
 // contiguous bytes per column and block, two columns per wave instruction),
 // column stride 36 pairs in LDS (16-byte operand reads spread over the banks:
-// 16 c16 + 4g words); Re A = Xr^T Xr + Xi^T Xi, Im A = Xr^T Xi - Xi^T Xr on
-// FP64 MFMA; waves reduced in the order ((w3 + w2) + w1) + w0.
+// 16 c16 + 4g words).  Each upper 16x16 tile takes three real MFMA products
+// (Gauss): P1 = Xr_I^T Xr_J, P2 = Xi_I^T Xi_J, P3 = (Xr_I - Xi_I)^T (Xr_J + Xi_J),
+// Re A = P1 + P2, Im A = P3 - P1 + P2 (Im A = Xr^T Xi - Xi^T Xr).  The rounding
+// error of every entry stays below a small multiple of eps ||x_i|| ||x_j||, the
+// column-scaled bound the off-diagonal test and the rotations rely on.  Wave w
+// takes row half w >> 1 of every block and tile set w & 1 (upper tiles 0-4 or
+// 5-9 in row-major order); the two row halves are added in a fixed order.
 constexpr int kGramRowsC = 32;
 constexpr int kGramLdcC = 36;
+
+template <int TS, bool FULL>
+__device__ __forceinline__ void gram3m_tiles(const double (&xr)[4], const double (&xi)[4], int nt, d4 (&q1)[5],
+                                             d4 (&q2)[5], d4 (&q3)[5]) {
+  constexpr int tI[2][5] = {{0, 0, 0, 0, 1}, {1, 1, 2, 2, 3}};
+  constexpr int tJ[2][5] = {{0, 1, 2, 3, 1}, {2, 3, 2, 3, 3}};
+#pragma unroll
+  for (int u = 0; u < 5; u++) {
+    const int I = tI[TS][u], J = tJ[TS][u];
+    if (FULL || J < nt) {
+      q1[u] = mfma16(xr[I], xr[J], q1[u]);
+      q2[u] = mfma16(xi[I], xi[J], q2[u]);
+      q3[u] = mfma16(xr[I] - xi[I], xr[J] + xi[J], q3[u]);
+    }
+  }
+}
+
+template <int TS>
+__device__ __forceinline__ void gram3m_store(double* __restrict__ out, int nt, int c16, int g, const d4 (&q1)[5],
+                                             const d4 (&q2)[5], const d4 (&q3)[5]) {
+  constexpr int tI[2][5] = {{0, 0, 0, 0, 1}, {1, 1, 2, 2, 3}};
+  constexpr int tJ[2][5] = {{0, 1, 2, 3, 1}, {2, 3, 2, 3, 3}};
+#pragma unroll
+  for (int u = 0; u < 5; u++) {
+    const int I = tI[TS][u], J = tJ[TS][u];
+    if (J < nt) {
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const size_t e = (size_t)(16 * I + 4 * v + g) * kMaxPivot + 16 * J + c16;
+        out[2 * e] = q1[u][v] + q2[u][v];
+        out[2 * e + 1] = (q3[u][v] - q1[u][v]) + q2[u][v];
+      }
+    }
+  }
+}
 
 __global__ __launch_bounds__(256, 2) void k_gram_c128(const double* __restrict__ G0, int ldg0, int n0,
                                                      const int* __restrict__ cols, const int* __restrict__ mlist,
@@ -301,78 +366,67 @@ __global__ __launch_bounds__(256, 2) void k_gram_c128(const double* __restrict__
     for (int i = 0; i < 8; i++) S[(2 * (wave + 4 * i) + lcol) * kGramLdcC + lrow] = ld[i];
   };
 
-  d4 are[10], aim[10];
+  const int hh = wave >> 1, ts = wave & 1;
+  d4 q1[5], q2[5], q3[5];
 #pragma unroll
-  for (int t = 0; t < 10; t++) {
-    are[t] = d4{0.0, 0.0, 0.0, 0.0};
-    aim[t] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int u = 0; u < 5; u++) {
+    q1[u] = d4{0.0, 0.0, 0.0, 0.0};
+    q2[u] = d4{0.0, 0.0, 0.0, 0.0};
+    q3[u] = d4{0.0, 0.0, 0.0, 0.0};
   }
   load_block(0);
   store_block(0);
   __syncthreads();
-  for (int b = 0; b < nblk; b++) {
-    if (b + 1 < nblk) load_block(b + 1);  // in flight during the MFMAs below
-    const dv2* S = smem + (b & 1) * (kMaxPivot * kGramLdcC);
+  // full: all four column tiles in use, no branch around the MFMAs
+  auto rows = [&](auto full) {
+    for (int b = 0; b < nblk; b++) {
+      if (b + 1 < nblk) load_block(b + 1);  // in flight during the MFMAs below
+      const dv2* S = smem + (b & 1) * (kMaxPivot * kGramLdcC);
 #pragma unroll
-    for (int kk = 0; kk < 2; kk++) {
-      const int row = 8 * wave + 4 * kk + g;
-      double xr[4], xi[4];
+      for (int kk = 0; kk < 4; kk++) {
+        const int row = 16 * hh + 4 * kk + g;
+        double xr[4], xi[4];
 #pragma unroll
-      for (int T = 0; T < 4; T++) {
-        const dv2 v = S[(16 * T + c16) * kGramLdcC + row];
-        xr[T] = v.x;
-        xi[T] = v.y;
-      }
-      int t = 0;
-#pragma unroll
-      for (int I = 0; I < 4; I++)
-#pragma unroll
-        for (int J = I; J < 4; J++) {
-          if (J < nt) {
-            are[t] = mfma16(xr[I], xr[J], are[t]);
-            are[t] = mfma16(xi[I], xi[J], are[t]);
-            aim[t] = mfma16(xr[I], xi[J], aim[t]);
-            aim[t] = mfma16(-xi[I], xr[J], aim[t]);
-          }
-          t++;
+        for (int T = 0; T < 4; T++) {
+          const dv2 v = S[(16 * T + c16) * kGramLdcC + row];
+          xr[T] = v.x;
+          xi[T] = v.y;
         }
+        if (ts == 0)
+          gram3m_tiles<0, decltype(full)::value>(xr, xi, nt, q1, q2, q3);
+        else
+          gram3m_tiles<1, decltype(full)::value>(xr, xi, nt, q1, q2, q3);
+      }
+      if (b + 1 < nblk) store_block((b + 1) & 1);
+      __syncthreads();
     }
-    if (b + 1 < nblk) store_block((b + 1) & 1);
-    __syncthreads();
-  }
-  // fixed-order reduction: ((w3 + w2) + w1) + w0, through LDS
-  d4* red = reinterpret_cast<d4*>(smem);  // [10][2][64]
-  for (int w = 3; w >= 1; w--) {
-    if (wave == w)
-      for (int t = 0; t < 10; t++) {
-        red[(t * 2 + 0) * 64 + lane] = are[t];
-        red[(t * 2 + 1) * 64 + lane] = aim[t];
-      }
-    __syncthreads();
-    if (wave == w - 1)
-      for (int t = 0; t < 10; t++) {
-        are[t] = red[(t * 2 + 0) * 64 + lane] + are[t];
-        aim[t] = red[(t * 2 + 1) * 64 + lane] + aim[t];
-      }
-    __syncthreads();
-  }
-  if (wave == 0) {
+  };
+  if (nt == 4)
+    rows(std::true_type{});
+  else
+    rows(std::false_type{});
+  // fixed-order reduction of the two row halves through LDS: half 0 + half 1
+  d4* red = reinterpret_cast<d4*>(smem);  // [2][15][64]
+  if (hh == 1)
+#pragma unroll
+    for (int u = 0; u < 5; u++) {
+      red[(ts * 15 + u) * 64 + lane] = q1[u];
+      red[(ts * 15 + 5 + u) * 64 + lane] = q2[u];
+      red[(ts * 15 + 10 + u) * 64 + lane] = q3[u];
+    }
+  __syncthreads();
+  if (hh == 0) {
+#pragma unroll
+    for (int u = 0; u < 5; u++) {
+      q1[u] = q1[u] + red[(ts * 15 + u) * 64 + lane];
+      q2[u] = q2[u] + red[(ts * 15 + 5 + u) * 64 + lane];
+      q3[u] = q3[u] + red[(ts * 15 + 10 + u) * 64 + lane];
+    }
     double* out = part + ((size_t)slot * nch + ch) * (2 * kMaxPivot * kMaxPivot);
-    int t = 0;
-#pragma unroll
-    for (int I = 0; I < 4; I++)
-#pragma unroll
-      for (int J = I; J < 4; J++) {
-        if (J < nt) {
-#pragma unroll
-          for (int v = 0; v < 4; v++) {
-            size_t e = (size_t)(16 * I + 4 * v + g) * kMaxPivot + 16 * J + c16;
-            out[2 * e] = are[t][v];
-            out[2 * e + 1] = aim[t][v];
-          }
-        }
-        t++;
-      }
+    if (ts == 0)
+      gram3m_store<0>(out, nt, c16, g, q1, q2, q3);
+    else
+      gram3m_store<1>(out, nt, c16, g, q1, q2, q3);
   }
 }
 
@@ -392,6 +446,7 @@ __global__ __launch_bounds__(256, 2) void k_update_c128(double* __restrict__ G0,
   if (ch * rows_per_chunk >= n) return;
   __shared__ double2 Ws[kMaxPivot * LDW];
   __shared__ int scol[kMaxPivot];
+  __shared__ size_t soff[kMaxPivot];  // clamped element offsets of the pivot's columns
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int c16 = lane & 15, g = lane >> 4;
   const int m = mlist[p];
@@ -402,22 +457,21 @@ __global__ __launch_bounds__(256, 2) void k_update_c128(double* __restrict__ G0,
     int c = e >> 6, r = e & 63;
     Ws[c * LDW + r] = (r < m && c < m) ? Wp[c * kMaxPivot + r] : double2{0.0, 0.0};
   }
-  if (tid < kMaxPivot) scol[tid] = (tid < m) ? cols[p * kMaxPivot + tid] : -1;
+  if (tid < kMaxPivot) {
+    const int pc = (tid < m) ? cols[p * kMaxPivot + tid] : -1;
+    scol[tid] = pc;
+    soff[tid] = (size_t)(pc >= 0 ? pc : cols[p * kMaxPivot]) * ldg;
+  }
   __syncthreads();
   gdbl2* Gc = as_global2(Gm);
   const int r0 = ch * rows_per_chunk;
   const int r1 = min(n, r0 + rows_per_chunk);
   // unconditional loads from clamped addresses, padding zeroed by a 0/1
   // factor (finite matrix): outstanding loads are counted, not drained
-  size_t coff[16];
+  // (offsets read from LDS at each load: register budget)
   unsigned okbits = 0;
 #pragma unroll
-  for (int kk = 0; kk < 16; kk++) {
-    const int pc = scol[4 * kk + g];
-    const bool ok = kk < ks && pc >= 0;
-    okbits |= ok ? (1u << kk) : 0u;
-    coff[kk] = (size_t)(ok ? pc : scol[0]) * ldg;
-  }
+  for (int kk = 0; kk < 16; kk++) okbits |= (kk < ks && 4 * kk + g < m) ? (1u << kk) : 0u;
   // the next strip's loads are issued before the current strip's MFMAs
   dv2 x[16], xn[16];
   int row0 = r0 + wave * 16;
@@ -426,40 +480,48 @@ __global__ __launch_bounds__(256, 2) void k_update_c128(double* __restrict__ G0,
     const unsigned ok = row < r1 ? okbits : 0u;
     const int rl = min(row, r1 - 1);
 #pragma unroll
-    for (int kk = 0; kk < 16; kk++) x[kk] = Gc[coff[kk] + rl] * ((ok >> kk) & 1u ? 1.0 : 0.0);
+    for (int kk = 0; kk < 16; kk++) x[kk] = Gc[soff[4 * kk + g] + rl] * ((ok >> kk) & 1u ? 1.0 : 0.0);
   }
-  for (; row0 < r1; row0 += 64) {
-    const int row = row0 + c16;
-    const int nrow = row + 64;
-    const unsigned nok = nrow < r1 ? okbits : 0u;
-    const int nrl = min(nrow, r1 - 1);
+  // full: a 64-column pivot, no branch around the MFMAs
+  auto rows = [&](auto full) {
+    for (; row0 < r1; row0 += 64) {
+      const int row = row0 + c16;
+      const int nrow = row + 64;
+      const unsigned nok = nrow < r1 ? okbits : 0u;
+      const int nrl = min(nrow, r1 - 1);
 #pragma unroll
-    for (int kk = 0; kk < 16; kk++) xn[kk] = Gc[coff[kk] + nrl] * ((nok >> kk) & 1u ? 1.0 : 0.0);
-    // three real products per complex one (Gauss): T1 = Xr Wr, T2 = Xi Wi,
-    // T3 = (Xr + Xi)(Wr + Wi); Re = T1 - T2, Im = T3 - T1 - T2 (transposed here)
+      for (int kk = 0; kk < 16; kk++) xn[kk] = Gc[soff[4 * kk + g] + nrl] * ((nok >> kk) & 1u ? 1.0 : 0.0);
+      // three real products per complex one (Gauss): T1 = Xr Wr, T2 = Xi Wi,
+      // T3 = (Xr + Xi)(Wr + Wi); Re = T1 - T2, Im = T3 - T1 - T2 (transposed here)
 #pragma unroll
-    for (int I = 0; I < 4; I++) {
-      if (I < nt) {
-        d4 t1 = d4{0.0, 0.0, 0.0, 0.0}, t2 = d4{0.0, 0.0, 0.0, 0.0}, t3 = d4{0.0, 0.0, 0.0, 0.0};
+      for (int I = 0; I < 4; I++) {
+        if (decltype(full)::value || I < nt) {
+          d4 t1 = d4{0.0, 0.0, 0.0, 0.0}, t2 = d4{0.0, 0.0, 0.0, 0.0}, t3 = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int kk = 0; kk < 16; kk++)
-          if (kk < ks) {
-            const double2 w = Ws[(16 * I + c16) * LDW + 4 * kk + g];
-            t1 = mfma16(w.x, x[kk].x, t1);
-            t2 = mfma16(w.y, x[kk].y, t2);
-            t3 = mfma16(w.x + w.y, x[kk].x + x[kk].y, t3);
+          for (int kk = 0; kk < 16; kk++)
+            if (decltype(full)::value || kk < ks) {
+              const double2 w = Ws[(16 * I + c16) * LDW + 4 * kk + g];
+              t1 = mfma16(w.x, x[kk].x, t1);
+              t2 = mfma16(w.y, x[kk].y, t2);
+              t3 = mfma16(w.x + w.y, x[kk].x + x[kk].y, t3);
+            }
+#pragma unroll
+          for (int v = 0; v < 4; v++) {
+            int oc = 16 * I + 4 * v + g;
+            int pc = scol[oc];
+            if (oc < m && row < r1) Gc[(size_t)pc * ldg + row] = dv2{t1[v] - t2[v], (t3[v] - t1[v]) - t2[v]};
           }
-#pragma unroll
-        for (int v = 0; v < 4; v++) {
-          int oc = 16 * I + 4 * v + g;
-          int pc = scol[oc];
-          if (oc < m && row < r1) Gc[(size_t)pc * ldg + row] = dv2{t1[v] - t2[v], (t3[v] - t1[v]) - t2[v]};
         }
+        __builtin_amdgcn_sched_barrier(0);  // one output tile at a time (register budget)
       }
-    }
 #pragma unroll
-    for (int kk = 0; kk < 16; kk++) x[kk] = xn[kk];
-  }
+      for (int kk = 0; kk < 16; kk++) x[kk] = xn[kk];
+    }
+  };
+  if (m == kMaxPivot)
+    rows(std::true_type{});
+  else
+    rows(std::false_type{});
 }
 
 // ---------------------------------------------------------------------------
