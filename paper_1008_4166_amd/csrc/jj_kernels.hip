@@ -97,35 +97,27 @@ __global__ __launch_bounds__(256, 2) void k_gram_f64(const double* __restrict__ 
   load_block(0);
   store_block(0);
   __syncthreads();
-  // full: all four column tiles in use (m > 48), the tile loop has no branch
-  // (a branch around each MFMA would serialise them)
-  auto rows = [&](auto full) {
-    for (int b = 0; b < nblk; b++) {
-      if (b + 1 < nblk) load_block(b + 1);  // in flight during the MFMAs below
-      const double* S = smem + (b & 1) * (kMaxPivot * kGramLdc);
+  for (int b = 0; b < nblk; b++) {
+    if (b + 1 < nblk) load_block(b + 1);  // in flight during the MFMAs below
+    const double* S = smem + (b & 1) * (kMaxPivot * kGramLdc);
 #pragma unroll
-      for (int kk = 0; kk < 4; kk++) {
-        const int row = 16 * wave + 4 * kk + g;
-        double xt[4];
+    for (int kk = 0; kk < 4; kk++) {
+      const int row = 16 * wave + 4 * kk + g;
+      double xt[4];
 #pragma unroll
-        for (int T = 0; T < 4; T++) xt[T] = S[(16 * T + c16) * kGramLdc + row];
-        int t = 0;
+      for (int T = 0; T < 4; T++) xt[T] = S[(16 * T + c16) * kGramLdc + row];
+      int t = 0;
 #pragma unroll
-        for (int I = 0; I < 4; I++)
+      for (int I = 0; I < 4; I++)
 #pragma unroll
-          for (int J = I; J < 4; J++) {
-            if (decltype(full)::value || J < nt) acc[t] = mfma16(xt[I], xt[J], acc[t]);
-            t++;
-          }
-      }
-      if (b + 1 < nblk) store_block((b + 1) & 1);
-      __syncthreads();
+        for (int J = I; J < 4; J++) {
+          if (J < nt) acc[t] = mfma16(xt[I], xt[J], acc[t]);
+          t++;
+        }
     }
-  };
-  if (nt == 4)
-    rows(std::true_type{});
-  else
-    rows(std::false_type{});
+    if (b + 1 < nblk) store_block((b + 1) & 1);
+    __syncthreads();
+  }
   // fixed-order reduction of the four waves: (w0 + w2) + (w1 + w3), through LDS
   d4* red = reinterpret_cast<d4*>(smem);  // [2][10][64]
   if (wave >= 2)
@@ -181,7 +173,6 @@ __global__ __launch_bounds__(256, 4) void k_update_f64(double* __restrict__ G0, 
   gdbl* G = as_global(Gm);
   __shared__ double Ws[kMaxPivot * LDW];
   __shared__ int scol[kMaxPivot];
-  __shared__ size_t soff[kMaxPivot];  // clamped element offsets of the pivot's columns
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int c16 = lane & 15, g = lane >> 4;
   const int m = mlist[p];
@@ -193,11 +184,7 @@ __global__ __launch_bounds__(256, 4) void k_update_f64(double* __restrict__ G0, 
     int c = e >> 6, r = e & 63;
     Ws[c * LDW + r] = (r < m && c < m) ? Wp[c * kMaxPivot + r] : 0.0;
   }
-  if (tid < kMaxPivot) {
-    const int pc = (tid < m) ? cols[p * kMaxPivot + tid] : -1;
-    scol[tid] = pc;
-    soff[tid] = (size_t)(pc >= 0 ? pc : cols[p * kMaxPivot]) * ldg;
-  }
+  if (tid < kMaxPivot) scol[tid] = (tid < m) ? cols[p * kMaxPivot + tid] : -1;
   __syncthreads();
 
   const int r0 = ch * rows_per_chunk;
@@ -207,11 +194,15 @@ __global__ __launch_bounds__(256, 4) void k_update_f64(double* __restrict__ G0, 
   // values are zeroed by a 0/1 factor (the matrix is finite: non-finite input
   // is rejected before the sweeps): no branch around a load, so outstanding
   // loads are counted instead of drained at every use.
-  // (the offsets are read from LDS at each load, which keeps four wavefronts
-  // per SIMD within the register budget)
+  size_t coff[16];
   unsigned okbits = 0;
 #pragma unroll
-  for (int kk = 0; kk < 16; kk++) okbits |= (kk < ks && 4 * kk + g < m) ? (1u << kk) : 0u;
+  for (int kk = 0; kk < 16; kk++) {
+    const int pc = scol[4 * kk + g];
+    const bool ok = kk < ks && pc >= 0;
+    okbits |= ok ? (1u << kk) : 0u;
+    coff[kk] = (size_t)(ok ? pc : scol[0]) * ldg;
+  }
   // the next strip's loads are issued before the current strip's MFMAs (the
   // scheduling barrier keeps them there)
   double x[16], xn[16];
@@ -221,48 +212,34 @@ __global__ __launch_bounds__(256, 4) void k_update_f64(double* __restrict__ G0, 
     const unsigned ok = row < r1 ? okbits : 0u;
     const int rl = min(row, r1 - 1);
 #pragma unroll
-    for (int kk = 0; kk < 16; kk++) x[kk] = G[soff[4 * kk + g] + rl] * ((ok >> kk) & 1u ? 1.0 : 0.0);
+    for (int kk = 0; kk < 16; kk++) x[kk] = G[coff[kk] + rl] * ((ok >> kk) & 1u ? 1.0 : 0.0);
   }
-  // full: a 64-column pivot; the MFMA loops have no branch (a branch around
-  // each MFMA would serialise them) and the four output tiles accumulate side
-  // by side.  Otherwise tiles and k-steps beyond m are skipped.
-  auto rows = [&](auto full) {
-    for (; row0 < r1; row0 += 64) {
-      const int row = row0 + c16;
-      const int nrow = row + 64;
-      const unsigned nok = nrow < r1 ? okbits : 0u;
-      const int nrl = min(nrow, r1 - 1);
+  for (; row0 < r1; row0 += 64) {
+    const int row = row0 + c16;
+    const int nrow = row + 64;
+    const unsigned nok = nrow < r1 ? okbits : 0u;
+    const int nrl = min(nrow, r1 - 1);
 #pragma unroll
-      for (int kk = 0; kk < 16; kk++) xn[kk] = G[soff[4 * kk + g] + nrl] * ((nok >> kk) & 1u ? 1.0 : 0.0);
-      __builtin_amdgcn_sched_barrier(0);
-      d4 acc[4];
+    for (int kk = 0; kk < 16; kk++) xn[kk] = G[coff[kk] + nrl] * ((nok >> kk) & 1u ? 1.0 : 0.0);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int I = 0; I < 4; I++) acc[I] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int I = 0; I < 4; I++) {
+      if (I < nt) {
+        d4 acc = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int kk = 0; kk < 16; kk++)
+        for (int kk = 0; kk < 16; kk++)
+          if (kk < ks) acc = mfma16(Ws[(16 * I + c16) * LDW + 4 * kk + g], x[kk], acc);
 #pragma unroll
-        for (int I = 0; I < 4; I++)
-          if (decltype(full)::value || (I < nt && kk < ks))
-            acc[I] = mfma16(Ws[(16 * I + c16) * LDW + 4 * kk + g], x[kk], acc[I]);
-#pragma unroll
-      for (int I = 0; I < 4; I++) {
-        if (decltype(full)::value || I < nt) {
-#pragma unroll
-          for (int v = 0; v < 4; v++) {
-            int oc = 16 * I + 4 * v + g;
-            int pc = scol[oc];
-            if (oc < m && row < r1) G[(size_t)pc * ldg + row] = acc[I][v];
-          }
+        for (int v = 0; v < 4; v++) {
+          int oc = 16 * I + 4 * v + g;
+          int pc = scol[oc];
+          if (oc < m && row < r1) G[(size_t)pc * ldg + row] = acc[v];
         }
       }
-#pragma unroll
-      for (int kk = 0; kk < 16; kk++) x[kk] = xn[kk];
     }
-  };
-  if (m == kMaxPivot)
-    rows(std::true_type{});
-  else
-    rows(std::false_type{});
+#pragma unroll
+    for (int kk = 0; kk < 16; kk++) x[kk] = xn[kk];
+  }
 }
 
 // ---------------------------------------------------------------------------
