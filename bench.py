@@ -338,6 +338,14 @@ def bench_config4(jj, torch, steps):
                 steps=steps, gen_seconds=gen_s, **res)
 
 
+def stored_long_oracle(k):
+    """Long-double oracle eigenvalues of workload k (the adjudicator), or None."""
+    path = os.path.join(ROOT, "tests", "golden", "config%d_lambda_long.txt" % k)
+    if not os.path.exists(path):
+        return None
+    return np.loadtxt(path, dtype=np.longdouble).astype(np.float64)
+
+
 def stored_oracle(k):
     path = os.path.join(ROOT, "tests", "golden", "config%d_lambda_double.txt" % k)
     if not os.path.exists(path):
@@ -438,6 +446,12 @@ def main():
     if ref is not None:
         acc["vs_oracle_max_rel"] = float(np.max(np.abs(lam_h - ref) / np.abs(ref)))
         acc["vs_oracle_p99_rel"] = float(np.percentile(np.abs(lam_h - ref) / np.abs(ref), 99))
+    ref_long = stored_long_oracle(WORKLOAD)
+    if ref_long is not None:
+        # the long-double oracle separates the input's conditioning from error
+        acc["vs_long_oracle_max_rel"] = float(np.max(np.abs(lam_h - ref_long) / np.abs(ref_long)))
+        if ref is not None:
+            acc["oracle_vs_long_oracle_max_rel"] = float(np.max(np.abs(ref - ref_long) / np.abs(ref_long)))
 
     out = {
         "metric": "eigenpairs/s (n=4096 FP64 solve); sweep time, FP64-MFMA fraction reported alongside",
@@ -493,6 +507,8 @@ def main():
         macc = {"vs_fp64_gpu_max_rel": float(np.max(np.abs(lam_m - lam_h) / np.abs(lam_h)))}
         if ref is not None:
             macc["vs_oracle_max_rel"] = float(np.max(np.abs(lam_m - ref) / np.abs(ref)))
+        if ref_long is not None:
+            macc["vs_long_oracle_max_rel"] = float(np.max(np.abs(lam_m - ref_long) / np.abs(ref_long)))
         out["mixed"] = dict(value=n * K / dtm, ms_per_step=dtm / K * 1e3, sweeps=[i["sweeps"] for i in minfos],
                             mixed_sweeps=[i["mixed_sweeps"] for i in minfos], accuracy=macc,
                             speedup_vs_fp64=ms_step / (dtm / K * 1e3))

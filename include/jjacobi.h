@@ -104,7 +104,9 @@ typedef struct jj_info {
                               Gram checks of the last sweep */
   double seconds;          /* wall-clock time of the solve */
   int mixed_sweeps;        /* sweeps that used the FP32 Gram (precision 1) */
-  int reserved[7];
+  int mixed_resolved;      /* pivot solves of those sweeps redone from an FP64 Gram block
+                              because the FP32 block could not be factored */
+  int reserved[6];
 } jj_info;
 
 /* Fill *opts with the defaults. */

@@ -142,10 +142,11 @@ inline void launch(F kernel, const dim3& grid, const dim3& block, unsigned shm, 
 
 // part[p][ch][r*64 + c] = sum over rows of chunk ch of conj(G[row, col(r)]) G[row, col(c)],
 // for the upper 16x16 tiles (tile(r) <= tile(c)).  Real: FP64 MFMA.
+// only (nullable): pivots with only[p] == 0 are skipped.
 void launch_gram_f64(const double* G, int ldg, int n, const PivotList& pl, int nch, int rows_per_chunk,
-                     double* part, hipStream_t stream, const Batch& b = Batch());
+                     double* part, hipStream_t stream, const Batch& b = Batch(), const int* only = nullptr);
 void launch_gram_c128(const double* G, int ldg, int n, const PivotList& pl, int nch, int rows_per_chunk,
-                      double* part, hipStream_t stream, const Batch& b = Batch());
+                      double* part, hipStream_t stream, const Batch& b = Batch(), const int* only = nullptr);
 
 // Same partials formed on FP32 MFMA from FP64 data converted on load (mixed-
 // precision pre-sweeps); the output is FP64 in the same layout.
@@ -162,12 +163,17 @@ void launch_gram_c64mix(const double* G, int ldg, int n, const PivotList& pl, in
 // mode: 0 full inner sweeps (inner_max), 1 off-diagonal pass only, 2 (batched
 // block-oriented) full pass at step 0 of the problem's sweep, else off-diagonal.
 // Only the first ceil(n / rows_per_chunk) partials of a pivot are summed.
+// refine (nullable, single problems): refine[p] is set to 1 for a pivot that
+// failed softly and to 0 otherwise.  only (nullable): pivots with only[p] == 0
+// return at once (a re-solve of the flagged pivots).
 void launch_pivot_f64(const double* part, int nch, int n, int rows_per_chunk, const PivotList& pl, double tol,
                       int inner_max, int inner_mode, int soft, double* W, int* rotflag, SweepStats* st,
-                      hipStream_t stream, const Batch& b = Batch());
+                      hipStream_t stream, const Batch& b = Batch(), int* refine = nullptr,
+                      const int* only = nullptr);
 void launch_pivot_c128(const double* part, int nch, int n, int rows_per_chunk, const PivotList& pl, double tol,
                        int inner_max, int inner_mode, int soft, double* W, int* rotflag, SweepStats* st,
-                       hipStream_t stream, const Batch& b = Batch());
+                       hipStream_t stream, const Batch& b = Batch(), int* refine = nullptr,
+                       const int* only = nullptr);
 
 // [G_i G_j] <- [G_i G_j] W_P in place for pivots with rotflag set.
 // nch_u: number of row chunks in the grid (0: ceil(n / rows_per_chunk)).

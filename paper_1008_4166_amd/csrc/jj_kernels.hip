@@ -43,11 +43,13 @@ constexpr int kGramLdc = 68;
 
 __global__ __launch_bounds__(256, 2) void k_gram_f64(const double* __restrict__ G0, int ldg0, int n0,
                                                      const int* __restrict__ cols, const int* __restrict__ mlist,
-                                                     int rows_per_chunk, double* __restrict__ part, Batch bt) {
+                                                     int rows_per_chunk, double* __restrict__ part, Batch bt,
+                                                     const int* __restrict__ only) {
   __shared__ double smem[2 * kMaxPivot * kGramLdc];  // two staged blocks; then the wave reduction
   const int nch = gridDim.x;
   int slot, ch;
   xcd_slot_chunk(slot, ch);
+  if (only != nullptr && !only[slot]) return;  // a re-solve launch: this pivot was solved
   int p = slot, ldg = ldg0, n = n0;
   double* Gm = const_cast<double*>(G0);
   SweepStats* stp = nullptr;
@@ -296,11 +298,13 @@ __device__ __forceinline__ void gram3m_store(double* __restrict__ out, int nt, i
 
 __global__ __launch_bounds__(256, 2) void k_gram_c128(const double* __restrict__ G0, int ldg0, int n0,
                                                      const int* __restrict__ cols, const int* __restrict__ mlist,
-                                                     int rows_per_chunk, double* __restrict__ part, Batch bt) {
+                                                     int rows_per_chunk, double* __restrict__ part, Batch bt,
+                                                     const int* __restrict__ only) {
   __shared__ dv2 smem[2 * kMaxPivot * kGramLdcC];  // two staged blocks; then the wave reduction
   const int nch = gridDim.x;
   int slot, ch;
   xcd_slot_chunk(slot, ch);
+  if (only != nullptr && !only[slot]) return;  // a re-solve launch: this pivot was solved
   int p = slot, ldg = ldg0, n = n0;
   double* Gm = const_cast<double*>(G0);
   SweepStats* stp = nullptr;
@@ -587,9 +591,9 @@ __global__ __launch_bounds__(256) void k_write_v(const double* __restrict__ G, i
 // launchers
 // ---------------------------------------------------------------------------
 void launch_gram_f64(const double* G, int ldg, int n, const PivotList& pl, int nch, int rows_per_chunk,
-                     double* part, hipStream_t stream, const Batch& b) {
+                     double* part, hipStream_t stream, const Batch& b, const int* only) {
   launch(k_gram_f64, dim3(nch, pl.count), dim3(256), 0, stream, G, ldg, n, pl.cols, pl.m,
-                     rows_per_chunk, part, b);
+                     rows_per_chunk, part, b, only);
 }
 
 void launch_update_f64(double* G, int ldg, int n, const PivotList& pl, const double* W, const int* rotflag,
@@ -600,9 +604,9 @@ void launch_update_f64(double* G, int ldg, int n, const PivotList& pl, const dou
 }
 
 void launch_gram_c128(const double* G, int ldg, int n, const PivotList& pl, int nch, int rows_per_chunk,
-                      double* part, hipStream_t stream, const Batch& b) {
+                      double* part, hipStream_t stream, const Batch& b, const int* only) {
   launch(k_gram_c128, dim3(nch, pl.count), dim3(256), 0, stream, G, ldg, n, pl.cols, pl.m,
-                     rows_per_chunk, part, b);
+                     rows_per_chunk, part, b, only);
 }
 
 void launch_update_c128(double* G, int ldg, int n, const PivotList& pl, const double* W, const int* rotflag,

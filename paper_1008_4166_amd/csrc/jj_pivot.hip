@@ -320,7 +320,8 @@ __global__ __launch_bounds__(64 * LPS) void k_pivot(const double* __restrict__ p
                                                     const int* __restrict__ nfirst,
                                                     const signed char* __restrict__ sgl, double tol, int inner_max,
                                                     int mode, int soft, double* __restrict__ Wout,
-                                                    int* __restrict__ rotflag, SweepStats* st0, Batch bt) {
+                                                    int* __restrict__ rotflag, SweepStats* st0, Batch bt,
+                                                    int* __restrict__ refine, const int* __restrict__ only) {
   typedef typename Scalar<CPLX>::T T;
   constexpr int NT = 64 * LPS;  // two halves of 32 slots
   constexpr int HT = 32 * LPS;  // threads of one half
@@ -336,6 +337,7 @@ __global__ __launch_bounds__(64 * LPS) void k_pivot(const double* __restrict__ p
   T* R = lds;
   T* W = lds + kMaxPivot * LDR;
   const int bslot = blockIdx.x, tid = threadIdx.x;
+  if (only != nullptr && !only[bslot]) return;  // a re-solve launch: this pivot was solved
   int p = bslot, n = n0, ldg_unused = 0;
   double* G_unused = nullptr;
   SweepStats* st = st0;
@@ -354,6 +356,7 @@ __global__ __launch_bounds__(64 * LPS) void k_pivot(const double* __restrict__ p
   const int m = mlist[p];
   const int n1 = nfirst[p], n2 = m - n1;
   if (tid < kMaxPivot) s_sg[tid] = sgl[p * kMaxPivot + tid];
+  if (refine != nullptr && tid == 0) refine[bslot] = 0;
   const signed char* sg = s_sg;  // signs of the pivot's columns, in LDS
 
   // ---- 1. A_P = sum of the chunk partials (upper 16x16 tiles), Hermitian fill ----
@@ -425,7 +428,10 @@ __global__ __launch_bounds__(64 * LPS) void k_pivot(const double* __restrict__ p
     if (tid == 0) {
       rotflag[bslot] = 0;
       if (s_bad) {
-        if (soft) atomicAdd(&st->soft_fail, 1);
+        if (soft) {
+          atomicAdd(&st->soft_fail, 1);
+          if (refine != nullptr) refine[bslot] = 1;
+        }
         else atomicOr(&st->breakdown, 1);
       }
     }
@@ -466,7 +472,10 @@ __global__ __launch_bounds__(64 * LPS) void k_pivot(const double* __restrict__ p
     if (s_bad) {
       if (tid == 0) {
         rotflag[bslot] = 0;
-        if (soft) atomicAdd(&st->soft_fail, 1);
+        if (soft) {
+          atomicAdd(&st->soft_fail, 1);
+          if (refine != nullptr) refine[bslot] = 1;
+        }
         else atomicOr(&st->breakdown, 1);
       }
       return;
@@ -797,8 +806,12 @@ __global__ __launch_bounds__(64 * LPS) void k_pivot(const double* __restrict__ p
     __syncthreads();
   }
   if (s_bad && tid == 0) {
-    if (soft) atomicAdd(&st->soft_fail, 1);
-    else atomicOr(&st->breakdown, 1);
+    if (soft) {
+      atomicAdd(&st->soft_fail, 1);
+      if (refine != nullptr) refine[bslot] = 1;
+    } else {
+      atomicOr(&st->breakdown, 1);
+    }
   }
 
   // ---- 5. W_P out ----
@@ -824,16 +837,16 @@ constexpr int kPivotLPS = 8;
 
 void launch_pivot_f64(const double* part, int nch, int n, int rows_per_chunk, const PivotList& pl, double tol,
                       int inner_max, int inner_mode, int soft, double* W, int* rotflag, SweepStats* st,
-                      hipStream_t stream, const Batch& b) {
+                      hipStream_t stream, const Batch& b, int* refine, const int* only) {
   launch((k_pivot<false, kPivotLPS>), dim3(pl.count), dim3(64 * kPivotLPS), 0, stream, part, nch, n,
-                     rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st, b);
+                     rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st, b, refine, only);
 }
 
 void launch_pivot_c128(const double* part, int nch, int n, int rows_per_chunk, const PivotList& pl, double tol,
                        int inner_max, int inner_mode, int soft, double* W, int* rotflag, SweepStats* st,
-                       hipStream_t stream, const Batch& b) {
+                       hipStream_t stream, const Batch& b, int* refine, const int* only) {
   launch((k_pivot<true, kPivotLPS>), dim3(pl.count), dim3(64 * kPivotLPS), 0, stream, part, nch, n,
-                     rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st, b);
+                     rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st, b, refine, only);
 }
 
 }  // namespace jj

@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -408,6 +409,7 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
     c.take<double>((size_t)nb_piv * nch * kMaxPivot * kMaxPivot * (cplx ? 2 : 1));
     c.take<double>((size_t)nb_piv * kMaxPivot * kMaxPivot * (cplx ? 2 : 1));
     c.take<int>(nb_piv);
+    c.take<int>(nb_piv);
     c.take<SweepStats>(1);
     c.take<int>(n);
     c.take<signed char>(n);
@@ -427,6 +429,7 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
   double* d_part = c.take<double>((size_t)nb_piv * nch * kMaxPivot * kMaxPivot * (cplx ? 2 : 1));
   double* d_W = c.take<double>((size_t)nb_piv * kMaxPivot * kMaxPivot * (cplx ? 2 : 1));
   int* d_rot = c.take<int>(nb_piv);
+  int* d_refine = c.take<int>(nb_piv);  // mixed sweeps: pivots to re-solve from an FP64 Gram block
   SweepStats* d_st = c.take<SweepStats>(1);
   int* d_colmap = c.take<int>(n);
   signed char* d_sgn = c.take<signed char>(n);
@@ -480,7 +483,7 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
   bool mixed = o.precision == 1;
   const double mix_switch = o.mixed_switch > 0.0 ? o.mixed_switch : 1e-5;
   const double tol_mix = std::max(tol, std::ldexp(1.0, -20));
-  int mixed_sweeps = 0;
+  int mixed_sweeps = 0, mixed_resolved = 0;
   int status = JJ_NOT_CONVERGED, sweep = 0;
   long long piv_rot = 0;
   double last_off = 0.0;
@@ -490,20 +493,40 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
   // pairing (Gram partials, pivot solves, update).  Profiled solves launch it
   // eagerly with per-kernel events; otherwise each variant (precision, diagonal
   // pass) is captured once per solve as a HIP graph and replayed per sweep.
+  // Gram block and pivot solve of the pairs in pl.  In a mixed sweep the Gram
+  // block is formed on FP32 MFMA and a pivot whose FP32 block cannot be
+  // factored (its scaled condition is beyond FP32, e.g. nearly parallel
+  // columns) is flagged and solved again, within the same step, from an FP64
+  // Gram block: the launches of that re-solve skip every unflagged pivot.
+  auto gram_pivot = [&](bool use_mix, const PivotList& pl, double* part, double* W, int* rot, int* refine,
+                        int mode, int imax, const std::function<void()>& after_first = nullptr) {
+    size_t k0 = prof.arm();
+    if (use_mix)
+      gram32(G, ldg, n, pl, nch, rows_g, part, stream, Batch());
+    else
+      gram64(G, ldg, n, pl, nch, rows_g, part, stream, Batch(), nullptr);
+    prof.done_kernel(JJ_K_GRAM, k0, pl.count);
+    if (after_first) after_first();
+    k0 = prof.arm();
+    pivot(part, nch, n, rows_g, pl, use_mix ? tol_mix : tol, imax, mode, use_mix, W, rot, d_st, stream, Batch(),
+          use_mix ? refine : nullptr, nullptr);
+    prof.done_kernel(JJ_K_PIVOT, k0, pl.count);
+    if (use_mix) {
+      k0 = prof.arm();
+      gram64(G, ldg, n, pl, nch, rows_g, part, stream, Batch(), refine);
+      prof.done_kernel(JJ_K_GRAM, k0, 0);
+      k0 = prof.arm();
+      pivot(part, nch, n, rows_g, pl, tol, imax, mode, 0, W, rot, d_st, stream, Batch(), nullptr, refine);
+      prof.done_kernel(JJ_K_PIVOT, k0, 0);
+    }
+  };
   auto enqueue_sweep = [&](bool use_mix, bool diag) {
-    auto gram = use_mix ? gram32 : gram64;
-    const double stol = use_mix ? tol_mix : tol;
     size_t k0 = prof.mark();
     launch_reset_stats(d_st, stream);
     prof.done(JJ_K_OTHER, k0, 0);
     if (diag) {
       PivotList dl{d_dcols, d_dsg, d_dm, d_dnf, P.nbl};
-      k0 = prof.arm();
-      gram(G, ldg, n, dl, nch, rows_g, d_part, stream, Batch());
-      prof.done_kernel(JJ_K_GRAM, k0, dl.count);
-      k0 = prof.arm();
-      pivot(d_part, nch, n, rows_g, dl, stol, inner_max, 0, use_mix, d_W, d_rot, d_st, stream, Batch());
-      prof.done_kernel(JJ_K_PIVOT, k0, dl.count);
+      gram_pivot(use_mix, dl, d_part, d_W, d_rot, d_refine, 0, inner_max);
       k0 = prof.arm();
       update(G, ldg, n, dl, d_W, d_rot, rows_u, stream, Batch(), 0);
       prof.done_kernel(JJ_K_UPDATE, k0, 0);
@@ -518,12 +541,7 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
       const bool block_oriented = o.inner_mode == 0;
       const int mode = (block_oriented && t > 0) ? 1 : 0;  // kernel mode 1: off-diagonal pass only
       const int imax = block_oriented ? 1 : inner_max;
-      k0 = prof.arm();
-      gram(G, ldg, n, pl, nch, rows_g, d_part, stream, Batch());
-      prof.done_kernel(JJ_K_GRAM, k0, pl.count);
-      k0 = prof.arm();
-      pivot(d_part, nch, n, rows_g, pl, stol, imax, mode, use_mix, d_W, d_rot, d_st, stream, Batch());
-      prof.done_kernel(JJ_K_PIVOT, k0, pl.count);
+      gram_pivot(use_mix, pl, d_part, d_W, d_rot, d_refine, mode, imax);
       k0 = prof.arm();
       update(G, ldg, n, pl, d_W, d_rot, rows_u, stream, Batch(), 0);
       prof.done_kernel(JJ_K_UPDATE, k0, 0);
@@ -556,8 +574,6 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
   };
   // captures the sequential sweep and returns its tasks (root node in *reset)
   auto capture_sweep_tasks = [&](bool use_mix, bool diag, hipGraphNode_t* reset, std::vector<Task>& tasks) {
-    auto gram = use_mix ? gram32 : gram64;
-    const double stol = use_mix ? tol_mix : tol;
     launch_reset_stats(d_st, stream);
     *reset = last_node();
     std::vector<int> owner(P.nbl, -1);  // last task to touch each block
@@ -570,9 +586,7 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
       double* part = d_part + s0 * nch * kMaxPivot * kMaxPivot * wsz;
       double* W = d_W + s0 * kMaxPivot * kMaxPivot * wsz;
       int* rot = d_rot + s0;
-      gram(G, ldg, n, pl, nch, rows_g, part, stream, Batch());
-      tk.first = last_node();
-      pivot(part, nch, n, rows_g, pl, stol, imax, mode, use_mix, W, rot, d_st, stream, Batch());
+      gram_pivot(use_mix, pl, part, W, rot, d_refine + s0, mode, imax, [&]() { tk.first = last_node(); });
       update(G, ldg, n, pl, W, rot, rows_u, stream, Batch(), 0);
       tk.last = last_node();
       for (int b : blocks) owner[b] = (int)tasks.size();
@@ -679,13 +693,12 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
     }
     if (o.history != nullptr && sweep <= o.history_len) o.history[sweep - 1] = off;
     if (use_mix) {
-      // leave FP32 Gram blocks once they are accurate enough to finish in FP64,
-      // once no pivot rotates, or as soon as some pivot's FP32 Gram block could
-      // not be factored (its scaled condition exceeds what FP32 resolves: such
-      // pivots, skipped, would otherwise hold the largest off-diagonal at the
-      // same value sweep after sweep)
+      // leave FP32 Gram blocks once they are accurate enough to finish in FP64
+      // or once no pivot rotates (pivots whose FP32 block could not be
+      // factored were re-solved from FP64 blocks within their step)
       mixed_sweeps++;
-      if (off < mix_switch || hst.pivots_rotated == 0 || hst.soft_fail) mixed = false;
+      mixed_resolved += hst.soft_fail;
+      if (off < mix_switch || hst.pivots_rotated == 0) mixed = false;
       continue;
     }
     if (hst.pivots_rotated == 0) {
@@ -725,6 +738,7 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
     info->final_offdiag = last_off;
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     info->mixed_sweeps = mixed_sweeps;
+    info->mixed_resolved = mixed_resolved;
   }
   return status;
 }
@@ -1042,12 +1056,12 @@ static int solve_batch(int count, const int* dtype, void* const* G, const signed
       if (grp[g].slots == 0) continue;
       PivotList pl{dg[g].cols, dg[g].sg, dg[g].m, dg[g].nfirst, grp[g].slots};
       if (!mixed) {
-        (g ? launch_gram_c128 : launch_gram_f64)(nullptr, 0, 0, pl, 1, rows_g[g], dg[g].part, s, bt[g]);
+        (g ? launch_gram_c128 : launch_gram_f64)(nullptr, 0, 0, pl, 1, rows_g[g], dg[g].part, s, bt[g], nullptr);
       } else {  // FP64 Gram for the problems in FP64 sweeps, FP32-MFMA Gram for the others
         Batch b64 = bt[g], b32 = bt[g];
         b64.prec_sel = 0;
         b32.prec_sel = 1;
-        (g ? launch_gram_c128 : launch_gram_f64)(nullptr, 0, 0, pl, 1, rows_g[g], dg[g].part, s, b64);
+        (g ? launch_gram_c128 : launch_gram_f64)(nullptr, 0, 0, pl, 1, rows_g[g], dg[g].part, s, b64, nullptr);
         (g ? launch_gram_c64mix : launch_gram_f32mix)(nullptr, 0, 0, pl, 1, rows_g[g], dg[g].part, s, b32);
       }
     }
@@ -1055,7 +1069,7 @@ static int solve_batch(int count, const int* dtype, void* const* G, const signed
       if (grp[g].slots == 0) continue;
       PivotList pl{dg[g].cols, dg[g].sg, dg[g].m, dg[g].nfirst, grp[g].slots};
       (g ? launch_pivot_c128 : launch_pivot_f64)(dg[g].part, 1, 0, rows_g[g], pl, btol, imax, pmode, 0, dg[g].W,
-                                                 dg[g].rot, nullptr, s, bt[g]);
+                                                 dg[g].rot, nullptr, s, bt[g], nullptr, nullptr);
     }
     for (int g = 0; g < 2; g++) {
       if (grp[g].slots == 0) continue;

@@ -236,3 +236,22 @@ def test_dataflow_sweep_graph_equals_eager(groups):
     assert ig["status"] == 0 and ig["sweeps"] == ie["sweeps"]
     assert np.array_equal(lg, le) and np.array_equal(Vg, Ve)
     check_parity(G, J, lg, "dataflow groups=%d" % groups)
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_mixed_resolves_pivots_fp32_cannot_factor(cplx):
+    # one column scaled to entries below 1e-23: its squares underflow in FP32,
+    # so every FP32 Gram block holding it has a zero diagonal entry and cannot
+    # be factored, while FP64 represents it with full relative accuracy (its
+    # eigenvalue is near 1e-46).  Mixed sweeps re-solve those pivots from FP64
+    # Gram blocks within the step and stay in FP32; the result meets the FP64
+    # parity bar.
+    n = 96
+    G, J, _ = jjgen.make(n, cplx, 40, 1e-3, 1.0, seed=8080 + cplx)
+    c = int(np.flatnonzero(J > 0)[3])
+    G[:, c] *= 1e-24 / np.max(np.abs(G[:, c]))
+    lg, V, info = gpu_solve(G, J, precision=1)
+    assert info["status"] == 0, info
+    assert info["mixed_resolved"] >= 1 and info["mixed_sweeps"] >= 2, info
+    check_parity(G, J, lg, "mixed re-solve cplx=%s" % cplx)
+    check_vectors(G, J, lg, V)
