@@ -148,8 +148,9 @@ void launch_gram_f64(const double* G, int ldg, int n, const PivotList& pl, int n
 void launch_gram_c128(const double* G, int ldg, int n, const PivotList& pl, int nch, int rows_per_chunk,
                       double* part, hipStream_t stream, const Batch& b = Batch(), const int* only = nullptr);
 
-// Same partials formed on FP32 MFMA from FP64 data converted on load (mixed-
-// precision pre-sweeps); the output is FP64 in the same layout.
+// Same partials formed on FP32 MFMA (mixed-precision pre-sweeps): the same
+// kernels with the operands rounded to FP32 as they leave LDS and FP32
+// accumulation within a chunk; the output is FP64 in the same layout.
 void launch_gram_f32mix(const double* G, int ldg, int n, const PivotList& pl, int nch, int rows_per_chunk,
                         double* part, hipStream_t stream, const Batch& b = Batch());
 void launch_gram_c64mix(const double* G, int ldg, int n, const PivotList& pl, int nch, int rows_per_chunk,

@@ -1,7 +1,7 @@
 // gfx950 kernels of the blocked one-sided hyperbolic J-Jacobi sweep (real FP64).
 //
 // One block step on a pair of block-columns (paper, Section 5.3, steps 1-4):
-//   k_gram_f64    A_P = [G_i G_j]^T [G_i G_j]                      (eq. 3.6)
+//   k_gram_real   A_P = [G_i G_j]^T [G_i G_j]                      (eq. 3.6)
 //   k_pivot_f64   Cholesky A_P = R^T R (eq. 3.8), one-sided J-Jacobi on the
 //                 columns of R accumulating W_P (eq. 3.12, Algorithms 3.1/3.2)
 //   k_update_f64  [G_i G_j] <- [G_i G_j] W_P                        (eq. 3.4)
@@ -23,6 +23,40 @@ __device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Accumulators of the Gram kernels: FP64 MFMA, or FP32 MFMA for the mixed-
+// precision pre-sweeps.  In the latter G stays FP64 in HBM and in LDS; the
+// operands are rounded to FP32 as they leave LDS and the products accumulate
+// on v_mfma_f32_16x16x4f32 (twice the FP64 matrix rate) over the chunk, the
+// chunk partials being added in FP64.  Only the Gram block (eq. 3.6) is formed
+// this way: the pivot solver computes every rotation and W_P in FP64 and the
+// update stays FP64, so each applied transformation is J-unitary to FP64
+// working precision (remark (a) of Section 2.3: inaccurate rotation
+// parameters do not harm the one-sided process as long as the applied
+// transformation is numerically J-unitary).  The two instructions place
+// results differently: element v of lane (c16, g) is D[4v + g][c16] for FP64
+// and D[4g + v][c16] for FP32 (measured on gfx950); the operand layouts agree.
+typedef float f4 __attribute__((ext_vector_type(4)));
+template <bool F32>
+struct GAcc;
+template <>
+struct GAcc<false> {
+  typedef d4 T;
+  static __device__ __forceinline__ T zero() { return d4{0.0, 0.0, 0.0, 0.0}; }
+  static __device__ __forceinline__ T mma(double a, double b, T c) { return mfma16(a, b, c); }
+  static __device__ __forceinline__ d4 wide(T c) { return c; }
+  static __device__ __forceinline__ int row(int v, int g) { return 4 * v + g; }
+};
+template <>
+struct GAcc<true> {
+  typedef f4 T;
+  static __device__ __forceinline__ T zero() { return f4{0.f, 0.f, 0.f, 0.f}; }
+  static __device__ __forceinline__ T mma(double a, double b, T c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32((float)a, (float)b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ d4 wide(T c) { return d4{(double)c[0], (double)c[1], (double)c[2], (double)c[3]}; }
+  static __device__ __forceinline__ int row(int v, int g) { return 4 * g + v; }
+};
+
 __device__ __forceinline__ void atomic_max_nonneg(unsigned long long* addr, double v) {
   atomicMax(addr, (unsigned long long)__double_as_longlong(v));
 }
@@ -41,7 +75,8 @@ __device__ __forceinline__ void atomic_max_nonneg(unsigned long long* addr, doub
 constexpr int kGramRows = 64;
 constexpr int kGramLdc = 68;
 
-__global__ __launch_bounds__(256, 2) void k_gram_f64(const double* __restrict__ G0, int ldg0, int n0,
+template <bool F32>
+__global__ __launch_bounds__(256, 2) void k_gram_real(const double* __restrict__ G0, int ldg0, int n0,
                                                      const int* __restrict__ cols, const int* __restrict__ mlist,
                                                      int rows_per_chunk, double* __restrict__ part, Batch bt,
                                                      const int* __restrict__ only) {
@@ -93,9 +128,9 @@ __global__ __launch_bounds__(256, 2) void k_gram_f64(const double* __restrict__ 
     for (int i = 0; i < 16; i++) S[(wave + 4 * i) * kGramLdc + lane] = ld[i];
   };
 
-  d4 acc[10];
+  typename GAcc<F32>::T ac[10];
 #pragma unroll
-  for (int t = 0; t < 10; t++) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int t = 0; t < 10; t++) ac[t] = GAcc<F32>::zero();
   load_block(0);
   store_block(0);
   __syncthreads();
@@ -113,7 +148,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_f64(const double* __restrict__ 
       for (int I = 0; I < 4; I++)
 #pragma unroll
         for (int J = I; J < 4; J++) {
-          if (J < nt) acc[t] = mfma16(xt[I], xt[J], acc[t]);
+          if (J < nt) ac[t] = GAcc<F32>::mma(xt[I], xt[J], ac[t]);
           t++;
         }
     }
@@ -121,6 +156,9 @@ __global__ __launch_bounds__(256, 2) void k_gram_f64(const double* __restrict__ 
     __syncthreads();
   }
   // fixed-order reduction of the four waves: (w0 + w2) + (w1 + w3), through LDS
+  d4 acc[10];
+#pragma unroll
+  for (int t = 0; t < 10; t++) acc[t] = GAcc<F32>::wide(ac[t]);
   d4* red = reinterpret_cast<d4*>(smem);  // [2][10][64]
   if (wave >= 2)
     for (int t = 0; t < 10; t++) red[((wave - 2) * 10 + t) * 64 + lane] = acc[t];
@@ -141,7 +179,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_f64(const double* __restrict__ 
         const d4 sacc = acc[t] + red[t * 64 + lane];
         if (J < nt) {
 #pragma unroll
-          for (int v = 0; v < 4; v++) out[(16 * I + 4 * v + g) * kMaxPivot + 16 * J + c16] = sacc[v];
+          for (int v = 0; v < 4; v++) out[(16 * I + GAcc<F32>::row(v, g)) * kMaxPivot + 16 * J + c16] = sacc[v];
         }
         t++;
       }
@@ -261,23 +299,24 @@ __global__ __launch_bounds__(256, 4) void k_update_f64(double* __restrict__ G0, 
 constexpr int kGramRowsC = 32;
 constexpr int kGramLdcC = 36;
 
-template <int TS, bool FULL>
-__device__ __forceinline__ void gram3m_tiles(const double (&xr)[4], const double (&xi)[4], int nt, d4 (&q1)[5],
-                                             d4 (&q2)[5], d4 (&q3)[5]) {
+template <int TS, bool FULL, bool F32>
+__device__ __forceinline__ void gram3m_tiles(const double (&xr)[4], const double (&xi)[4], int nt,
+                                             typename GAcc<F32>::T (&q1)[5], typename GAcc<F32>::T (&q2)[5],
+                                             typename GAcc<F32>::T (&q3)[5]) {
   constexpr int tI[2][5] = {{0, 0, 0, 0, 1}, {1, 1, 2, 2, 3}};
   constexpr int tJ[2][5] = {{0, 1, 2, 3, 1}, {2, 3, 2, 3, 3}};
 #pragma unroll
   for (int u = 0; u < 5; u++) {
     const int I = tI[TS][u], J = tJ[TS][u];
     if (FULL || J < nt) {
-      q1[u] = mfma16(xr[I], xr[J], q1[u]);
-      q2[u] = mfma16(xi[I], xi[J], q2[u]);
-      q3[u] = mfma16(xr[I] - xi[I], xr[J] + xi[J], q3[u]);
+      q1[u] = GAcc<F32>::mma(xr[I], xr[J], q1[u]);
+      q2[u] = GAcc<F32>::mma(xi[I], xi[J], q2[u]);
+      q3[u] = GAcc<F32>::mma(xr[I] - xi[I], xr[J] + xi[J], q3[u]);
     }
   }
 }
 
-template <int TS>
+template <int TS, bool F32>
 __device__ __forceinline__ void gram3m_store(double* __restrict__ out, int nt, int c16, int g, const d4 (&q1)[5],
                                              const d4 (&q2)[5], const d4 (&q3)[5]) {
   constexpr int tI[2][5] = {{0, 0, 0, 0, 1}, {1, 1, 2, 2, 3}};
@@ -288,7 +327,7 @@ __device__ __forceinline__ void gram3m_store(double* __restrict__ out, int nt, i
     if (J < nt) {
 #pragma unroll
       for (int v = 0; v < 4; v++) {
-        const size_t e = (size_t)(16 * I + 4 * v + g) * kMaxPivot + 16 * J + c16;
+        const size_t e = (size_t)(16 * I + GAcc<F32>::row(v, g)) * kMaxPivot + 16 * J + c16;
         out[2 * e] = q1[u][v] + q2[u][v];
         out[2 * e + 1] = (q3[u][v] - q1[u][v]) + q2[u][v];
       }
@@ -296,7 +335,8 @@ __device__ __forceinline__ void gram3m_store(double* __restrict__ out, int nt, i
   }
 }
 
-__global__ __launch_bounds__(256, 2) void k_gram_c128(const double* __restrict__ G0, int ldg0, int n0,
+template <bool F32>
+__global__ __launch_bounds__(256, 2) void k_gram_cplx(const double* __restrict__ G0, int ldg0, int n0,
                                                      const int* __restrict__ cols, const int* __restrict__ mlist,
                                                      int rows_per_chunk, double* __restrict__ part, Batch bt,
                                                      const int* __restrict__ only) {
@@ -348,12 +388,12 @@ __global__ __launch_bounds__(256, 2) void k_gram_c128(const double* __restrict__
   };
 
   const int hh = wave >> 1, ts = wave & 1;
-  d4 q1[5], q2[5], q3[5];
+  typename GAcc<F32>::T a1[5], a2[5], a3[5];
 #pragma unroll
   for (int u = 0; u < 5; u++) {
-    q1[u] = d4{0.0, 0.0, 0.0, 0.0};
-    q2[u] = d4{0.0, 0.0, 0.0, 0.0};
-    q3[u] = d4{0.0, 0.0, 0.0, 0.0};
+    a1[u] = GAcc<F32>::zero();
+    a2[u] = GAcc<F32>::zero();
+    a3[u] = GAcc<F32>::zero();
   }
   load_block(0);
   store_block(0);
@@ -374,9 +414,9 @@ __global__ __launch_bounds__(256, 2) void k_gram_c128(const double* __restrict__
           xi[T] = v.y;
         }
         if (ts == 0)
-          gram3m_tiles<0, decltype(full)::value>(xr, xi, nt, q1, q2, q3);
+          gram3m_tiles<0, decltype(full)::value, F32>(xr, xi, nt, a1, a2, a3);
         else
-          gram3m_tiles<1, decltype(full)::value>(xr, xi, nt, q1, q2, q3);
+          gram3m_tiles<1, decltype(full)::value, F32>(xr, xi, nt, a1, a2, a3);
       }
       if (b + 1 < nblk) store_block((b + 1) & 1);
       __syncthreads();
@@ -386,7 +426,14 @@ __global__ __launch_bounds__(256, 2) void k_gram_c128(const double* __restrict__
     rows(std::true_type{});
   else
     rows(std::false_type{});
-  // fixed-order reduction of the two row halves through LDS: half 0 + half 1
+  // fixed-order reduction of the two row halves through LDS, in FP64: half 0 + half 1
+  d4 q1[5], q2[5], q3[5];
+#pragma unroll
+  for (int u = 0; u < 5; u++) {
+    q1[u] = GAcc<F32>::wide(a1[u]);
+    q2[u] = GAcc<F32>::wide(a2[u]);
+    q3[u] = GAcc<F32>::wide(a3[u]);
+  }
   d4* red = reinterpret_cast<d4*>(smem);  // [2][15][64]
   if (hh == 1)
 #pragma unroll
@@ -405,9 +452,9 @@ __global__ __launch_bounds__(256, 2) void k_gram_c128(const double* __restrict__
     }
     double* out = part + ((size_t)slot * nch + ch) * (2 * kMaxPivot * kMaxPivot);
     if (ts == 0)
-      gram3m_store<0>(out, nt, c16, g, q1, q2, q3);
+      gram3m_store<0, F32>(out, nt, c16, g, q1, q2, q3);
     else
-      gram3m_store<1>(out, nt, c16, g, q1, q2, q3);
+      gram3m_store<1, F32>(out, nt, c16, g, q1, q2, q3);
   }
 }
 
@@ -592,8 +639,14 @@ __global__ __launch_bounds__(256) void k_write_v(const double* __restrict__ G, i
 // ---------------------------------------------------------------------------
 void launch_gram_f64(const double* G, int ldg, int n, const PivotList& pl, int nch, int rows_per_chunk,
                      double* part, hipStream_t stream, const Batch& b, const int* only) {
-  launch(k_gram_f64, dim3(nch, pl.count), dim3(256), 0, stream, G, ldg, n, pl.cols, pl.m,
+  launch(k_gram_real<false>, dim3(nch, pl.count), dim3(256), 0, stream, G, ldg, n, pl.cols, pl.m,
                      rows_per_chunk, part, b, only);
+}
+
+void launch_gram_f32mix(const double* G, int ldg, int n, const PivotList& pl, int nch, int rows_per_chunk,
+                        double* part, hipStream_t stream, const Batch& b) {
+  launch(k_gram_real<true>, dim3(nch, pl.count), dim3(256), 0, stream, G, ldg, n, pl.cols, pl.m, rows_per_chunk,
+         part, b, (const int*)nullptr);
 }
 
 void launch_update_f64(double* G, int ldg, int n, const PivotList& pl, const double* W, const int* rotflag,
@@ -605,8 +658,14 @@ void launch_update_f64(double* G, int ldg, int n, const PivotList& pl, const dou
 
 void launch_gram_c128(const double* G, int ldg, int n, const PivotList& pl, int nch, int rows_per_chunk,
                       double* part, hipStream_t stream, const Batch& b, const int* only) {
-  launch(k_gram_c128, dim3(nch, pl.count), dim3(256), 0, stream, G, ldg, n, pl.cols, pl.m,
+  launch(k_gram_cplx<false>, dim3(nch, pl.count), dim3(256), 0, stream, G, ldg, n, pl.cols, pl.m,
                      rows_per_chunk, part, b, only);
+}
+
+void launch_gram_c64mix(const double* G, int ldg, int n, const PivotList& pl, int nch, int rows_per_chunk,
+                        double* part, hipStream_t stream, const Batch& b) {
+  launch(k_gram_cplx<true>, dim3(nch, pl.count), dim3(256), 0, stream, G, ldg, n, pl.cols, pl.m, rows_per_chunk,
+         part, b, (const int*)nullptr);
 }
 
 void launch_update_c128(double* G, int ldg, int n, const PivotList& pl, const double* W, const int* rotflag,
