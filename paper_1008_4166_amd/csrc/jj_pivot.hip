@@ -364,7 +364,7 @@ __global__ __launch_bounds__(64 * LPS) void k_pivot(const double* __restrict__ p
   // chunk loads of EB tiles are issued together, then summed in chunk order.
   const T* P = reinterpret_cast<const T*>(part) + (size_t)bslot * nch * (kMaxPivot * kMaxPivot);
   {
-    constexpr int EB = CPLX ? 2 : 4;
+    constexpr int EB = CPLX ? 3 : 5;  // all (real) or two rounds (complex) of loads in flight
     for (int u0 = tid; u0 < 10 * 256; u0 += EB * NT) {
       T v[EB][kMaxChunks];
       int rr[EB], cc[EB];
@@ -398,11 +398,9 @@ __global__ __launch_bounds__(64 * LPS) void k_pivot(const double* __restrict__ p
     s_cnt = 0;
   }
   __syncthreads();
-  for (int e = tid; e < kMaxPivot * kMaxPivot; e += NT) {
-    int r = e >> 6, c = e & 63;
-    if (r < m && c < m && r > c) R[c * LDR + r] = conj_of(R[r * LDR + c]);
-  }
-  __syncthreads();
+  // Only the upper triangle is formed: the off-diagonal test reads it, and the
+  // Cholesky below reads and writes no entry left of the diagonal that feeds
+  // an entry on or right of it (it writes zeros there).
 
   // ---- 2. scaled off-diagonal test; zero or non-finite diagonal = breakdown ----
   if (tid < kMaxPivot) {
@@ -467,6 +465,16 @@ __global__ __launch_bounds__(64 * LPS) void k_pivot(const double* __restrict__ p
         }
       }
       if (tid == 0) s_bad = bad;
+    } else {
+      // W_P = I, written by the other wavefronts meanwhile
+      for (int e = tid - 64; e < kMaxPivot * kMaxPivot; e += NT - 64) {
+        int r = e & 63, c = e >> 6;
+        if (r < m && c < m) {
+          T one = zero_of(T());
+          if constexpr (CPLX) one.x = (r == c) ? 1.0 : 0.0; else one = (r == c) ? 1.0 : 0.0;
+          W[c * LDR + r] = one;
+        }
+      }
     }
     __syncthreads();
     if (s_bad) {
@@ -480,15 +488,6 @@ __global__ __launch_bounds__(64 * LPS) void k_pivot(const double* __restrict__ p
       }
       return;
     }
-    for (int e = tid; e < kMaxPivot * kMaxPivot; e += NT) {
-      int r = e & 63, c = e >> 6;
-      if (r < m && c < m) {
-        T one = zero_of(T());
-        if constexpr (CPLX) one.x = (r == c) ? 1.0 : 0.0; else one = (r == c) ? 1.0 : 0.0;
-        W[c * LDR + r] = one;
-      }
-    }
-    __syncthreads();
   }
 
   // ---- 4. inner sweeps ----
