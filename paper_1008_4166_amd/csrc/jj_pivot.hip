@@ -268,10 +268,21 @@ __device__ __forceinline__ d4p mfma16p(double a, double b, d4p c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// Trailing update of the Cholesky after the panel of rows r0..r0+15 (one
-// wavefront): S[16I.., 16J..] -= R_p[:, 16I..]^* R_p[:, 16J..] for the tiles
-// r0 + 16 <= 16I <= 16J < m.  MFMA lane l supplies A[l%16][l/16], B[l/16][l%16]
-// and holds D[4v + l/16][l%16]; S and R share the column-major LDS array.
+// Trailing update of the Cholesky after the panel of rows r0..r0+15:
+// S[16I.., 16J..] -= R_p[:, 16I..]^* R_p[:, 16J..] for the tiles
+// r0 + 16 <= 16I <= 16J < m.  Real: one wavefront takes all tiles (four MFMAs
+// each); complex: one tile per wavefront (sixteen MFMAs each, at most six
+// tiles; the tiles are disjoint and the panel rows they read are not written).
+// MFMA lane l supplies A[l%16][l/16], B[l/16][l%16] and holds
+// D[4v + l/16][l%16]; S and R share the column-major LDS array.
+__device__ __forceinline__ bool trailing_tile(int r0, int m, int wave, int& I, int& J) {
+  const int tn = (m + 15) >> 4;
+  int k = wave;
+  for (I = (r0 >> 4) + 1; I < tn; I++)
+    for (J = I; J < tn; J++)
+      if (k-- == 0) return true;
+  return false;
+}
 __device__ __forceinline__ void chol_trailing(double* R, int r0, int m, int lane) {
   const int c16 = lane & 15, g = lane >> 4;
   const int tn = (m + 15) >> 4;
@@ -288,11 +299,10 @@ __device__ __forceinline__ void chol_trailing(double* R, int r0, int m, int lane
     }
 }
 // Complex: Re -= Xr^T Yr + Xi^T Yi, Im -= Xr^T Yi - Xi^T Yr.
-__device__ __forceinline__ void chol_trailing(double2* R, int r0, int m, int lane) {
+__device__ __forceinline__ void chol_trailing(double2* R, int r0, int m, int wave, int lane) {
   const int c16 = lane & 15, g = lane >> 4;
-  const int tn = (m + 15) >> 4;
-  for (int I = (r0 >> 4) + 1; I < tn; I++)
-    for (int J = I; J < tn; J++) {
+  int I, J;
+  if (trailing_tile(r0, m, wave, I, J)) {
       d4p are, aim;
 #pragma unroll
       for (int v = 0; v < 4; v++) {
@@ -443,30 +453,9 @@ __global__ __launch_bounds__(64 * LPS) void k_pivot(const double* __restrict__ p
   // r_ki read from lane i.  The rows below the panel take the same update as
   // 16x16 tiles on the FP64 matrix cores (S_IJ -= R_pI^* R_pJ), through LDS.
   {
-    int bad = 0;
-    if (tid < 64) {
-      const int lane = tid;
-      for (int r0 = 0; r0 < m; r0 += 16) {
-        const int kn = min(16, m - r0);
-        T s[16];
-#pragma unroll
-        for (int ii = 0; ii < 16; ii++)
-          s[ii] = (lane >= r0 && lane < m && ii < kn) ? R[lane * LDR + r0 + ii] : zero_of(T());
-        bad = kn == 16 ? chol_panel<true>(s, r0, kn, lane) : chol_panel<false>(s, r0, kn, lane);
-        if (bad) break;
-        // rows r0..r0+kn-1 of R, zero left of the diagonal and beyond column m
-#pragma unroll
-        for (int ii = 0; ii < 16; ii++)
-          if (ii < kn) R[lane * LDR + r0 + ii] = (lane < r0 + ii || lane >= m) ? zero_of(T()) : s[ii];
-        if (r0 + 16 < m) {
-          wave_sync();
-          chol_trailing(R, r0, m, lane);
-          wave_sync();
-        }
-      }
-      if (tid == 0) s_bad = bad;
-    } else {
-      // W_P = I, written by the other wavefronts meanwhile
+    const int wave = tid >> 6, lane = tid & 63;
+    if (tid >= 64) {
+      // W_P = I, written by the other wavefronts while the first panel is factored
       for (int e = tid - 64; e < kMaxPivot * kMaxPivot; e += NT - 64) {
         int r = e & 63, c = e >> 6;
         if (r < m && c < m) {
@@ -476,7 +465,47 @@ __global__ __launch_bounds__(64 * LPS) void k_pivot(const double* __restrict__ p
         }
       }
     }
-    __syncthreads();
+    auto panel = [&](int r0) {  // wavefront 0; false if a pivot is not positive
+      const int kn = min(16, m - r0);
+      T s[16];
+#pragma unroll
+      for (int ii = 0; ii < 16; ii++)
+        s[ii] = (lane >= r0 && lane < m && ii < kn) ? R[lane * LDR + r0 + ii] : zero_of(T());
+      const int bad = kn == 16 ? chol_panel<true>(s, r0, kn, lane) : chol_panel<false>(s, r0, kn, lane);
+      if (bad) return false;
+      // rows r0..r0+kn-1 of R, zero left of the diagonal and beyond column m
+#pragma unroll
+      for (int ii = 0; ii < 16; ii++)
+        if (ii < kn) R[lane * LDR + r0 + ii] = (lane < r0 + ii || lane >= m) ? zero_of(T()) : s[ii];
+      return true;
+    };
+    if constexpr (CPLX) {
+      // trailing tiles spread over the wavefronts, a workgroup barrier per panel
+      for (int r0 = 0; r0 < m; r0 += 16) {
+        if (wave == 0 && !panel(r0) && lane == 0) s_bad = 1;
+        __syncthreads();
+        if (s_bad) break;
+        if (r0 + 16 < m) {
+          chol_trailing(R, r0, m, wave, lane);
+          __syncthreads();
+        }
+      }
+    } else {
+      // wavefront 0 alone, wavefront-level synchronisation
+      if (wave == 0) {
+        int ok = 1;
+        for (int r0 = 0; r0 < m && ok; r0 += 16) {
+          ok = panel(r0);
+          if (ok && r0 + 16 < m) {
+            wave_sync();
+            chol_trailing(R, r0, m, lane);
+            wave_sync();
+          }
+        }
+        if (lane == 0 && !ok) s_bad = 1;
+      }
+      __syncthreads();
+    }
     if (s_bad) {
       if (tid == 0) {
         rotflag[bslot] = 0;
