@@ -324,8 +324,12 @@ __device__ __forceinline__ void chol_trailing(double2* R, int r0, int m, int wav
     }
 }
 
-template <bool CPLX, int LPS>
-__global__ __launch_bounds__(64 * LPS) void k_pivot(const double* __restrict__ part, int nch, int n0,
+// DENSE: at most 128 registers per lane (a few spills), so that two real
+// workgroups share a CU; used for batched launches, whose thousands of pivots
+// are bound by the latency of each one and gain from a second workgroup per CU.
+// Single solves (one pivot per CU at most) use the unconstrained build.
+template <bool CPLX, int LPS, bool DENSE>
+__global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE ? 4 : 1, 8))) void k_pivot(const double* __restrict__ part, int nch, int n0,
                                                     int rows_per_chunk, const int* __restrict__ mlist,
                                                     const int* __restrict__ nfirst,
                                                     const signed char* __restrict__ sgl, double tol, int inner_max,
@@ -866,14 +870,18 @@ constexpr int kPivotLPS = 8;
 void launch_pivot_f64(const double* part, int nch, int n, int rows_per_chunk, const PivotList& pl, double tol,
                       int inner_max, int inner_mode, int soft, double* W, int* rotflag, SweepStats* st,
                       hipStream_t stream, const Batch& b, int* refine, const int* only) {
-  launch((k_pivot<false, kPivotLPS>), dim3(pl.count), dim3(64 * kPivotLPS), 0, stream, part, nch, n,
+  if (b.slot_prob != nullptr)
+    launch((k_pivot<false, kPivotLPS, true>), dim3(pl.count), dim3(64 * kPivotLPS), 0, stream, part, nch, n,
+           rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st, b, refine, only);
+  else
+    launch((k_pivot<false, kPivotLPS, false>), dim3(pl.count), dim3(64 * kPivotLPS), 0, stream, part, nch, n,
                      rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st, b, refine, only);
 }
 
 void launch_pivot_c128(const double* part, int nch, int n, int rows_per_chunk, const PivotList& pl, double tol,
                        int inner_max, int inner_mode, int soft, double* W, int* rotflag, SweepStats* st,
                        hipStream_t stream, const Batch& b, int* refine, const int* only) {
-  launch((k_pivot<true, kPivotLPS>), dim3(pl.count), dim3(64 * kPivotLPS), 0, stream, part, nch, n,
+  launch((k_pivot<true, kPivotLPS, false>), dim3(pl.count), dim3(64 * kPivotLPS), 0, stream, part, nch, n,
                      rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st, b, refine, only);
 }
 
