@@ -23,6 +23,28 @@ def test_header_symbols_exported():
         assert hasattr(lib, name)
 
 
+def test_struct_layouts_match_header(tmp_path):
+    # the ctypes mirrors of jj_opts, jj_info and jj_profile against the C
+    # compiler's layout of the header (field offsets and sizes)
+    import subprocess
+    structs = {"jj_opts": jj._lib.jj_opts, "jj_info": jj._lib.jj_info, "jj_profile": jj._lib.jj_profile}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "jjacobi.h"', "int main(void) {"]
+    for sname, cls in structs.items():
+        lines.append('  printf("%s size %%zu\\n", sizeof(%s));' % (sname, sname))
+        for fname, _ in cls._fields_:
+            lines.append('  printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (sname, fname, sname, fname))
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = dict(line.rsplit(" ", 1) for line in subprocess.check_output([str(exe)], text=True).splitlines())
+    for sname, cls in structs.items():
+        assert int(out["%s size" % sname]) == ctypes.sizeof(cls), sname
+        for fname, _ in cls._fields_:
+            assert int(out["%s.%s" % (sname, fname)]) == getattr(cls, fname).offset, (sname, fname)
+
+
 @pytest.mark.parametrize("n,nt", [(1, 32), (2, 32), (3, 32), (64, 32), (65, 32), (100, 16), (4096, 32),
                                   (4097, 32), (1024, 32), (8192, 32), (5, 2), (33, 4), (7, 7)])
 def test_partition(n, nt):
