@@ -1089,17 +1089,50 @@ static int solve_batch(int count, const int* dtype, void* const* G, const signed
   if (left > 0) {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    ck(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
-    for (int r = 0; r < kRound; r++) one_step();
-    ck(hipStreamEndCapture(s, &graph), "end capture");
-    ck(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "instantiate");
+    auto capture = [&]() {
+      if (exec != nullptr) (void)hipGraphExecDestroy(exec);
+      if (graph != nullptr) (void)hipGraphDestroy(graph);
+      exec = nullptr;
+      graph = nullptr;
+      ck(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+      for (int r = 0; r < kRound; r++) one_step();
+      ck(hipStreamEndCapture(s, &graph), "end capture");
+      ck(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "instantiate");
+    };
+    capture();
+    // Slot compaction: once the active problems fall to 3/5 of those the slot
+    // lists were built for, the lists are rebuilt from the active problems
+    // only and the round is captured again, so that finished problems stop
+    // taking workgroups (each slot's W_P, partials and flags live only within a
+    // step, so slots can be renumbered between rounds).
+    int basis = left;
+    std::vector<int> act(count);
     for (long long done = 0; left > 0 && done < step_cap; done += kRound) {
       ck(hipGraphLaunch(exec, s), "graph launch");
       ck(hipMemcpyAsync(&left, d_active_count, sizeof(int), hipMemcpyDeviceToHost, s), "D2H");
       ck(hipStreamSynchronize(s), "sync");
+      if (left > 0 && 5LL * left <= 3LL * basis) {
+        ck(hipMemcpyAsync(act.data(), d_active, count * sizeof(int), hipMemcpyDeviceToHost, s), "D2H");
+        ck(hipStreamSynchronize(s), "sync");
+        for (int g = 0; g < 2; g++) {
+          GroupTables& T = grp[g];
+          std::vector<int> sp, sk;
+          for (size_t q = 0; q < T.slot_prob.size(); q++)
+            if (act[T.slot_prob[q]]) {
+              sp.push_back(T.slot_prob[q]);
+              sk.push_back(T.slot_k[q]);
+            }
+          T.slots = (int)sp.size();
+          up(dg[g].slot_prob, sp.data(), sp.size() * sizeof(int));
+          up(dg[g].slot_k, sk.data(), sk.size() * sizeof(int));
+          ck(hipStreamSynchronize(s), "sync");
+        }
+        basis = left;
+        capture();
+      }
     }
-    hipGraphExecDestroy(exec);
-    hipGraphDestroy(graph);
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
   }
 
   launch_batch_finalize(count, d_gptr, d_ldg, d_nrow, d_width, d_colmap, d_cm_off, d_sgn, d_lam, d_V, d_ldv, d_dwork,
