@@ -230,10 +230,6 @@ __device__ __forceinline__ double2 readlane_of(double2 v, int l) {
 
 // |a| f for a scale factor f > 0 (the scaled off-diagonal measure)
 __device__ __forceinline__ double abs_scaled(double a, double f) { return fabs(a) * f; }
-__device__ __forceinline__ double abs_scaled(double2 a, double f) {
-  const double x = a.x * f, y = a.y * f;
-  return sqrt_nr(fma(x, x, y * y));
-}
 
 // One Cholesky panel (rows r0..r0+kn-1) held as s[ii] = S[r0 + ii][lane]:
 // row k of R is row k of S times 1/sqrt(s_kk), then each later row i of the
@@ -378,7 +374,7 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
   // chunk loads of EB tiles are issued together, then summed in chunk order.
   const T* P = reinterpret_cast<const T*>(part) + (size_t)bslot * nch * (kMaxPivot * kMaxPivot);
   {
-    constexpr int EB = CPLX ? 3 : 5;  // all (real) or two rounds (complex) of loads in flight
+    constexpr int EB = 5;  // all loads of the partials in flight at once
     for (int u0 = tid; u0 < 10 * 256; u0 += EB * NT) {
       T v[EB][kMaxChunks];
       int rr[EB], cc[EB];
@@ -424,10 +420,19 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
     s_dinv[tid] = okd ? rsqrt_nr(d) : 0.0;
   }
   __syncthreads();
+  // complex: the largest squared modulus, one square root at the end
   double off = 0.0;
   for (int e = tid; e < kMaxPivot * kMaxPivot; e += NT) {
     const int r = e & 63, c = e >> 6;
-    if (r < c && c < m) off = fmax(off, abs_scaled(R[c * LDR + r], s_dinv[r] * s_dinv[c]));
+    if (r < c && c < m) {
+      if constexpr (CPLX) {
+        const T a = R[c * LDR + r];
+        const double f = s_dinv[r] * s_dinv[c], x = a.x * f, y = a.y * f;
+        off = fmax(off, fma(x, x, y * y));
+      } else {
+        off = fmax(off, abs_scaled(R[c * LDR + r], s_dinv[r] * s_dinv[c]));
+      }
+    }
   }
 #pragma unroll
   for (int msk = 32; msk > 0; msk >>= 1) off = fmax(off, __shfl_xor(off, msk));
@@ -435,6 +440,7 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
   __syncthreads();
   off = redv[0];
   for (int w = 1; w < NT / 64; w++) off = fmax(off, redv[w]);
+  if constexpr (CPLX) off = sqrt_nr(off);
   if (tid == 0) atomic_max_nonneg(&st->max_off_bits, isfinite(off) ? off : 1.0e300);
   if (s_bad || off <= tol) {
     if (tid == 0) {
