@@ -1,10 +1,13 @@
-// gfx950 kernels of the blocked one-sided hyperbolic J-Jacobi sweep (real FP64).
+// gfx950 kernels of the blocked one-sided hyperbolic J-Jacobi sweep: the Gram
+// and update kernels (real and complex; FP32 instances of the Gram kernels for
+// the mixed-precision pre-sweeps) and the finalisation.
 //
 // One block step on a pair of block-columns (paper, Section 5.3, steps 1-4):
-//   k_gram_real   A_P = [G_i G_j]^T [G_i G_j]                      (eq. 3.6)
-//   k_pivot_f64   Cholesky A_P = R^T R (eq. 3.8), one-sided J-Jacobi on the
-//                 columns of R accumulating W_P (eq. 3.12, Algorithms 3.1/3.2)
-//   k_update_f64  [G_i G_j] <- [G_i G_j] W_P                        (eq. 3.4)
+//   k_gram_real / k_gram_cplx      A_P = [G_i G_j]^* [G_i G_j]        (eq. 3.6)
+//   k_pivot (jj_pivot.hip)         Cholesky A_P = R^* R (eq. 3.8), one-sided
+//                                  J-Jacobi on the columns of R accumulating
+//                                  W_P (eq. 3.12, Algorithms 3.1/3.2)
+//   k_update_f64 / k_update_c128   [G_i G_j] <- [G_i G_j] W_P         (eq. 3.4)
 // and the finalisation lambda_i = j_i ||g_i||^2, v_i = g_i/||g_i|| (eq. 2.10).
 //
 // MFMA: v_mfma_f64_16x16x4f64.  Lane l supplies A[l%16][l/16] and B[l/16][l%16]

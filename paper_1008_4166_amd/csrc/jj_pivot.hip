@@ -11,8 +11,11 @@
 //   (a) within each of the two blocks: circle round-robin, R and W_P in LDS;
 //   (b) across the blocks: slot k keeps column k of the first block in
 //       registers for the whole pass while the columns of the second block
-//       move one slot per round through an LDS ring, so that slot k meets
-//       second-block column (k + q) mod L in round q.
+//       move between slots: for two equal power-of-two blocks by the XOR
+//       schedule (slot k meets second-block column k ^ gray(q) in round q;
+//       moves by DPP or lane permutes within a wavefront, through LDS for the
+//       3 of 31 moves that cross wavefronts), otherwise through an LDS ring
+//       (slot k meets second-block column (k + q) mod L in round q).
 // Block-oriented steps (Section 3.4 / Algorithm 5.1) run (b) once; full
 // diagonalisation repeats (a)+(b) until an inner sweep applies no rotation.
 #include "jj_device.h"
