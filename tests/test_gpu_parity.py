@@ -285,3 +285,27 @@ def test_full_size_config4_properties():
     res = np.linalg.norm(HV - V * lg[idx][None, :], axis=0) / np.sum(np.abs(G) ** 2)
     assert np.max(res) <= 64 * n * EPS, res
     assert np.max(np.abs(V.conj().T @ V - np.eye(len(idx)))) <= 16 * n * EPS
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_leading_dimensions_and_padding(cplx):
+    # G with ldg > n whose padding rows hold NaN, V with ldv > n: the padding is
+    # never read or written, and the results are bitwise those of the packed solve
+    jj = _lib()
+    n, ldg, ldv = 150, 157, 153
+    G, J, _ = jjgen.make(n, cplx, 60, 1e-6, 1.0, seed=2718 + cplx)
+    dt = torch.complex128 if cplx else torch.float64
+    Gp = torch.full((n, ldg), float("nan"), dtype=dt, device="cuda")  # row c = column c of G, padded
+    Gp[:, :n] = torch.from_numpy(np.ascontiguousarray(G.T)).cuda()
+    Vp = torch.full((n, ldv), 7.0, dtype=dt, device="cuda")
+    lam = torch.empty(n, dtype=torch.float64, device="cuda")
+    o = jj.make_opts(stream=torch.cuda.current_stream().cuda_stream)
+    info = jj.jj_info()
+    st = jj.jjacobi_solve_ex(1 if cplx else 0, Gp.data_ptr(), J, n, ldg, lam.data_ptr(), Vp.data_ptr(), ldv,
+                             0.0, 0, o, info)
+    torch.cuda.synchronize()
+    assert st == 0
+    assert torch.all(Vp[:, n:] == 7.0)
+    lref, Vref, _ = gpu_solve(G, J)
+    assert np.array_equal(lam.cpu().numpy(), lref)
+    assert np.array_equal(Vp[:, :n].cpu().numpy().T, Vref)
