@@ -854,6 +854,12 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
       atomicOr(&st->breakdown, 1);
     }
   }
+  if (s_bad && soft && refine != nullptr) {
+    // handed on to the FP64 re-solve of this step, which writes W_P, the flag
+    // and the counters of this pivot
+    if (tid == 0) rotflag[bslot] = 0;
+    return;
+  }
 
   // ---- 5. W_P out ----
   const int rotated = total > 0;
