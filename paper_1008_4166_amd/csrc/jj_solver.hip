@@ -537,8 +537,10 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
       if (pl.count == 0) continue;
       // Block-oriented variant (Section 5.3): the first step of a sweep makes one
       // full pass over its pivots (covering every diagonal block), the other
-      // steps one pass over the off-diagonal block only.
-      const bool block_oriented = o.inner_mode == 0;
+      // steps one pass over the off-diagonal block only.  With two blocks the
+      // single pivot is the whole matrix, and it is diagonalised in full
+      // (Section 3.3) instead of one pass per sweep.
+      const bool block_oriented = o.inner_mode == 0 && P.nbl > 2;
       const int mode = (block_oriented && t > 0) ? 1 : 0;  // kernel mode 1: off-diagonal pass only
       const int imax = block_oriented ? 1 : inner_max;
       gram_pivot(use_mix, pl, d_part, d_W, d_rot, d_refine, mode, imax);
@@ -603,7 +605,7 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
         run_task(blocks, dl, s0, 0, inner_max);
       }
     }
-    const bool block_oriented = o.inner_mode == 0;
+    const bool block_oriented = o.inner_mode == 0 && P.nbl > 2;
     const int imax = block_oriented ? 1 : inner_max;
     for (int t = 0; t < P.nsteps; t++) {
       const int count = P.count[t];
