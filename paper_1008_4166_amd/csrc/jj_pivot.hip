@@ -236,12 +236,22 @@ __device__ __forceinline__ double abs_scaled(double a, double f) { return fabs(a
 
 // One Cholesky panel (rows r0..r0+kn-1) held as s[ii] = S[r0 + ii][lane]:
 // row k of R is row k of S times 1/sqrt(s_kk), then each later row i of the
-// panel subtracts conj(r_ki) * (row k of R), r_ki being lane i's entry.  Returns
-// nonzero if a pivot s_kk is not positive and finite (the caller stops after
-// the panel; the steps after it run on meaningless values).
-template <bool FULL, typename T>
-__device__ __forceinline__ int chol_panel(T (&s)[16], int r0, int kn, int lane) {
+// panel subtracts conj(r_ki) * (row k of R), r_ki being lane i's entry.
+// DEFER > 0: only the next row's factor r_k,k+1 is taken by a lane read (the
+// dependent chain from one diagonal entry to the next); row k also goes to the
+// 16 x 64 LDS buffer rb, from which the later rows' factors are read, and
+// their updates are applied one row later, beside the next square root.
+// DEFER == 1 reads the factors one row ahead into registers (about 30 more
+// values held); DEFER == 2 prefetches only the one that the next row's chain
+// needs and reads the others where they are used.  Every entry takes the
+// updates of rows 0, 1, ... in that order, with the same operations.
+// Returns nonzero if a pivot s_kk is not positive and finite (the caller stops
+// after the panel; the steps after it run on meaningless values).
+template <bool FULL, int DEFER, typename T>
+__device__ __forceinline__ int chol_panel(T (&s)[16], int r0, int kn, int lane, T* rb) {
   int bad = 0;
+  T rp[16];  // DEFER == 1: row kk - 1 of R at columns r0 + ii, ii >= kk + 1
+  T rn = zero_of(T());  // DEFER == 2: r_{kk-1, kk+1}
 #pragma unroll
   for (int kk = 0; kk < 16; kk++) {
     if (FULL || kk < kn) {
@@ -250,11 +260,42 @@ __device__ __forceinline__ int chol_panel(T (&s)[16], int r0, int kn, int lane) 
       const double y = rsqrt_nr(d);
       s[kk] = scale(s[kk], y);
       if (lane == r0 + kk) s[kk] = scale(one_like(s[kk]), d * y);  // real positive diagonal
+      if constexpr (DEFER > 0) {
+        rb[64 * kk + lane] = s[kk];  // every lane: no branch in the unrolled panel
+        if (kk + 1 < 16 && (FULL || kk + 1 < kn)) {
+          if (kk >= 1)
+            s[kk + 1] = lin2(1.0, s[kk + 1], -1.0,
+                             cmul_conj_first(conj_of(DEFER == 1 ? rp[kk + 1] : rn), s[kk - 1]));
+          const T rk1 = readlane_of(s[kk], r0 + kk + 1);
+          s[kk + 1] = lin2(1.0, s[kk + 1], -1.0, cmul_conj_first(conj_of(rk1), s[kk]));
+        }
+        wave_sync();  // the row's LDS writes before the reads below
+        if constexpr (DEFER == 1) {
+          T rc[16];
 #pragma unroll
-      for (int ii = kk + 1; ii < 16; ii++) {
-        if (FULL || ii < kn) {
-          const T rki = readlane_of(s[kk], r0 + ii);
-          s[ii] = lin2(1.0, s[ii], -1.0, cmul_conj_first(conj_of(rki), s[kk]));
+          for (int ii = kk + 2; ii < 16; ii++)
+            if (FULL || ii < kn) rc[ii] = rb[64 * kk + r0 + ii];
+#pragma unroll
+          for (int ii = kk + 2; ii < 16; ii++) {
+            if (kk >= 1 && (FULL || ii < kn))
+              s[ii] = lin2(1.0, s[ii], -1.0, cmul_conj_first(conj_of(rp[ii]), s[kk - 1]));
+            rp[ii] = rc[ii];
+          }
+        } else {
+          const T rnew = (kk + 2 < 16 && (FULL || kk + 2 < kn)) ? rb[64 * kk + r0 + kk + 2] : zero_of(T());
+#pragma unroll
+          for (int ii = kk + 2; ii < 16; ii++)
+            if (kk >= 1 && (FULL || ii < kn))
+              s[ii] = lin2(1.0, s[ii], -1.0, cmul_conj_first(conj_of(rb[64 * (kk - 1) + r0 + ii]), s[kk - 1]));
+          rn = rnew;
+        }
+      } else {
+#pragma unroll
+        for (int ii = kk + 1; ii < 16; ii++) {
+          if (FULL || ii < kn) {
+            const T rki = readlane_of(s[kk], r0 + ii);
+            s[ii] = lin2(1.0, s[ii], -1.0, cmul_conj_first(conj_of(rki), s[kk]));
+          }
         }
       }
     }
@@ -347,6 +388,7 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
   __shared__ int ring_sg[2][32];
   __shared__ double prm[2][32][5];  // rotation of each slot in a cross round: cs, sn, -sigma sn, phase
   __shared__ int prc[2][32];        // 1: that rotation is applied
+  __shared__ T s_rb[DENSE ? 1 : 16 * 64];  // Cholesky: the rows of the current panel
   T* R = lds;
   T* W = lds + kMaxPivot * LDR;
   const int bslot = blockIdx.x, tid = threadIdx.x;
@@ -484,7 +526,9 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
 #pragma unroll
       for (int ii = 0; ii < 16; ii++)
         s[ii] = (lane >= r0 && lane < m && ii < kn) ? R[lane * LDR + r0 + ii] : zero_of(T());
-      const int bad = kn == 16 ? chol_panel<true>(s, r0, kn, lane) : chol_panel<false>(s, r0, kn, lane);
+      constexpr int DEFER = DENSE ? 0 : (CPLX ? 2 : 1);
+      const int bad = kn == 16 ? chol_panel<true, DEFER>(s, r0, kn, lane, s_rb)
+                               : chol_panel<false, DEFER>(s, r0, kn, lane, s_rb);
       if (bad) return false;
       // rows r0..r0+kn-1 of R, zero left of the diagonal and beyond column m
 #pragma unroll
