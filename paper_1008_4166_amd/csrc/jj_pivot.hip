@@ -368,7 +368,11 @@ __device__ __forceinline__ void chol_trailing(double2* R, int r0, int m, int wav
 // workgroups share a CU; used for batched launches, whose thousands of pivots
 // are bound by the latency of each one and gain from a second workgroup per CU.
 // Single solves (one pivot per CU at most) use the unconstrained build.
-template <bool CPLX, int LPS, bool DENSE>
+// CHOL: the Cholesky panel form (chol_panel's DEFER).  The deferred forms
+// shorten the factorisation; launches that diagonalise their pivots in full
+// spend nearly all their time in the inner sweeps, which compile about 3%
+// faster beside the lane-read form, and take that one.
+template <bool CPLX, int LPS, bool DENSE, int CHOL>
 __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE ? 4 : 1, 8))) void k_pivot(const double* __restrict__ part, int nch, int n0,
                                                     int rows_per_chunk, const int* __restrict__ mlist,
                                                     const int* __restrict__ nfirst,
@@ -388,7 +392,7 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
   __shared__ int ring_sg[2][32];
   __shared__ double prm[2][32][5];  // rotation of each slot in a cross round: cs, sn, -sigma sn, phase
   __shared__ int prc[2][32];        // 1: that rotation is applied
-  __shared__ T s_rb[DENSE ? 1 : 16 * 64];  // Cholesky: the rows of the current panel
+  __shared__ T s_rb[CHOL == 0 ? 1 : 16 * 64];  // Cholesky: the rows of the current panel
   T* R = lds;
   T* W = lds + kMaxPivot * LDR;
   const int bslot = blockIdx.x, tid = threadIdx.x;
@@ -526,9 +530,8 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
 #pragma unroll
       for (int ii = 0; ii < 16; ii++)
         s[ii] = (lane >= r0 && lane < m && ii < kn) ? R[lane * LDR + r0 + ii] : zero_of(T());
-      constexpr int DEFER = DENSE ? 0 : (CPLX ? 2 : 1);
-      const int bad = kn == 16 ? chol_panel<true, DEFER>(s, r0, kn, lane, s_rb)
-                               : chol_panel<false, DEFER>(s, r0, kn, lane, s_rb);
+      const int bad = kn == 16 ? chol_panel<true, CHOL>(s, r0, kn, lane, s_rb)
+                               : chol_panel<false, CHOL>(s, r0, kn, lane, s_rb);
       if (bad) return false;
       // rows r0..r0+kn-1 of R, zero left of the diagonal and beyond column m
 #pragma unroll
@@ -929,18 +932,23 @@ constexpr int kPivotLPS = 8;
 void launch_pivot_f64(const double* part, int nch, int n, int rows_per_chunk, const PivotList& pl, double tol,
                       int inner_max, int inner_mode, int soft, double* W, int* rotflag, SweepStats* st,
                       hipStream_t stream, const Batch& b, int* refine, const int* only) {
+  // batched launches: two workgroups per CU, lane-read Cholesky (register budget)
   if (b.slot_prob != nullptr)
-    launch((k_pivot<false, kPivotLPS, true>), dim3(pl.count), dim3(64 * kPivotLPS), 0, stream, part, nch, n,
+    launch((k_pivot<false, kPivotLPS, true, 0>), dim3(pl.count), dim3(64 * kPivotLPS), 0, stream, part, nch, n,
+           rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st, b, refine, only);
+  // full diagonalisation (mode 0, several inner sweeps): the lane-read Cholesky
+  else if (inner_mode == 0 && inner_max > 1)
+    launch((k_pivot<false, kPivotLPS, false, 0>), dim3(pl.count), dim3(64 * kPivotLPS), 0, stream, part, nch, n,
            rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st, b, refine, only);
   else
-    launch((k_pivot<false, kPivotLPS, false>), dim3(pl.count), dim3(64 * kPivotLPS), 0, stream, part, nch, n,
-                     rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st, b, refine, only);
+    launch((k_pivot<false, kPivotLPS, false, 1>), dim3(pl.count), dim3(64 * kPivotLPS), 0, stream, part, nch, n,
+           rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st, b, refine, only);
 }
 
 void launch_pivot_c128(const double* part, int nch, int n, int rows_per_chunk, const PivotList& pl, double tol,
                        int inner_max, int inner_mode, int soft, double* W, int* rotflag, SweepStats* st,
                        hipStream_t stream, const Batch& b, int* refine, const int* only) {
-  launch((k_pivot<true, kPivotLPS, false>), dim3(pl.count), dim3(64 * kPivotLPS), 0, stream, part, nch, n,
+  launch((k_pivot<true, kPivotLPS, false, 2>), dim3(pl.count), dim3(64 * kPivotLPS), 0, stream, part, nch, n,
                      rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st, b, refine, only);
 }
 
