@@ -757,7 +757,10 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
 
 // Autotuner: block width per (dtype, size bucket), chosen by timing two
 // candidate widths on a copy of the first problem of the bucket (two sweeps
-// each) and cached for the process.
+// each) and cached for the process.  Each candidate first runs one untimed
+// sweep: the first solves of a process grow the workspace cache, and that
+// cost, charged to whichever candidate ran first, outweighed two sweeps of a
+// small problem and picked the slower width.
 
 
 static int tune_block_width(int dtype, void* G, const signed char* J, int n, int ldg, hipStream_t stream) {
@@ -774,6 +777,16 @@ static int tune_block_width(int dtype, void* G, const signed char* J, int n, int
   int best = 32;
   float best_ms = 1e30f;
   const int cand[2] = {32, 16};
+  for (int c : cand) {  // untimed: workspace growth and first launches
+    ck(hipMemcpy2DAsync(Gc, (size_t)n * w * sizeof(double), G, (size_t)ldg * w * sizeof(double),
+                        (size_t)n * w * sizeof(double), n, hipMemcpyDeviceToDevice, stream),
+       "copy tune");
+    jj_opts o;
+    jjacobi_default_opts(&o);
+    o.stream = stream;
+    o.block_width = c;
+    solve_one(dtype, Gc, J, n, n, lam, V, n, 0.0, 1, o, nullptr, false);
+  }
   for (int c : cand) {
     ck(hipMemcpy2DAsync(Gc, (size_t)n * w * sizeof(double), G, (size_t)ldg * w * sizeof(double),
                         (size_t)n * w * sizeof(double), n, hipMemcpyDeviceToDevice, stream),
