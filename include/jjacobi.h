@@ -63,8 +63,10 @@ extern "C" {
 typedef struct jj_opts {
   void* stream;          /* hipStream_t to order the work on; NULL: null stream */
   int block_width;       /* target block width n_t of eq. 3.2 (at most 32); 0: library
-                            choice: 32, or for n >= 1024 the faster of 16 and 32 timed over
-                            two sweeps on the first solve of each (dtype, size) class */
+                            choice: 32, or the faster of 16 and 32 timed over two sweeps
+                            (each after one untimed sweep) on the first problem of each
+                            (dtype, size) class seen by the process: single solves with
+                            n >= 1024, every batched problem with n > 64 */
   int inner_max_sweeps;  /* cap on inner sweeps of one pivot solve (Algorithm 3.2 max_it);
                             0: 12 */
   int diag_pass;         /* diagonal-block pre-processing (Algorithm 3.3, first inner loop):
