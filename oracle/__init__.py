@@ -18,7 +18,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "libjjoracle.so")
-_SRC = [os.path.join(_HERE, "jj_oracle.c"), os.path.join(_HERE, "jj_oracle_body.inc")]
+_SRC = [os.path.join(_HERE, "jj_oracle.c"), os.path.join(_HERE, "jj_oracle_body.inc"),
+        os.path.join(_HERE, "jj_bp_body.inc")]
 CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-shared", "-fPIC"]
 
 
@@ -47,6 +48,15 @@ def load(path=_SO):
         f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                       ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                       ctypes.c_void_p, ctypes.c_void_p]
+        f = getattr(lib, "jjo_solve_rect_" + sfx)
+        f.restype = ctypes.c_int
+        f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                      ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                      ctypes.c_void_p, ctypes.c_void_p]
+        f = getattr(lib, "jjo_bp_factor_" + sfx)
+        f.restype = ctypes.c_int
+        f.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_void_p,
+                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     _lib_cache[path] = lib
     return lib
 
@@ -58,8 +68,9 @@ def _ptr(a):
 def solve(G, J, tol=0.0, max_sweeps=0, precision="double", vectors=True, final_G=False, lib=None):
     """Eigenpairs of H = G J G^* by the oracle.
 
-    G: (n, n) float64 or complex128 array (any memory order; copied to
-    column-major).  J: n signs.  precision: "double" or "long" (long double
+    G: (m, n) float64 or complex128 array with m >= n (square, or the
+    rectangular full-column-rank factor of a singular H; any memory order;
+    copied to column-major).  J: n signs.  V has m rows.  precision: "double" or "long" (long double
     working precision).  Returns a dict with ``lam`` (sorted descending; float64
     or longdouble), ``V`` (columns are unit eigenvectors, or None), ``status``,
     ``sweeps``, ``rotations``, ``order`` (input column of each eigenvalue) and,
@@ -67,7 +78,7 @@ def solve(G, J, tol=0.0, max_sweeps=0, precision="double", vectors=True, final_G
     """
     lib = lib or load()
     G = np.asarray(G)
-    n = G.shape[0]
+    m, n = G.shape
     cplx = np.iscomplexobj(G)
     Gf = np.asfortranarray(G, dtype=np.complex128 if cplx else np.float64)
     Jc = np.ascontiguousarray(np.asarray(J), dtype=np.int8)
@@ -75,15 +86,43 @@ def solve(G, J, tol=0.0, max_sweeps=0, precision="double", vectors=True, final_G
     sfx = ("l" if long else "") + ("z" if cplx else "d")
     rdt = np.longdouble if long else np.float64
     lam = np.zeros(max(n, 1), dtype=rdt)
-    V = np.zeros((n, n), dtype=np.complex128 if cplx else np.float64, order="F") if vectors else None
+    V = np.zeros((m, n), dtype=np.complex128 if cplx else np.float64, order="F") if vectors else None
     Gfin = None
     if final_G:
-        Gfin = np.zeros((n, n), dtype=(np.clongdouble if long else np.complex128) if cplx else rdt, order="F")
+        Gfin = np.zeros((m, n), dtype=(np.clongdouble if long else np.complex128) if cplx else rdt, order="F")
     order = np.zeros(max(n, 1), dtype=np.int32)
     sweeps = ctypes.c_int(0)
     rots = ctypes.c_longlong(0)
-    st = getattr(lib, "jjo_solve_" + sfx)(_ptr(Gf), _ptr(Jc), n, max(n, 1), float(tol), int(max_sweeps),
+    st = getattr(lib, "jjo_solve_rect_" + sfx)(_ptr(Gf), _ptr(Jc), m, n, max(m, 1), float(tol), int(max_sweeps),
                                            _ptr(lam), _ptr(V), _ptr(Gfin), _ptr(order),
                                            ctypes.byref(sweeps), ctypes.byref(rots))
     return dict(lam=lam[:n], V=V, status=st, sweeps=sweeps.value, rotations=rots.value,
                 order=order[:n], G=Gfin)
+
+
+def bp_factor(H, tol=0.0, precision="double", lib=None):
+    """Front end H -> G J G^* by the oracle (Bunch-Parlett with complete
+    pivoting, then the diagonalisation of the 2x2 blocks of D; paper,
+    Section 2.2, eq. 2.5).
+
+    H: (n, n) Hermitian float64 or complex128 (only its lower triangle is
+    read).  Returns a dict with ``G`` (n x r, full column rank), ``J`` (r
+    signs), ``rank`` r, ``perm`` (row i of the lower block-triangular factor is
+    row perm[i] of H), ``pivsize`` (1 or 2 per column: the order of the block of
+    D it came from) and ``status``."""
+    lib = lib or load()
+    H = np.asarray(H)
+    n = H.shape[0]
+    cplx = np.iscomplexobj(H)
+    Hf = np.asfortranarray(H, dtype=np.complex128 if cplx else np.float64)
+    sfx = ("l" if precision == "long" else "") + ("z" if cplx else "d")
+    G = np.zeros((n, n), dtype=np.complex128 if cplx else np.float64, order="F")
+    J = np.zeros(max(n, 1), dtype=np.int8)
+    perm = np.zeros(max(n, 1), dtype=np.int32)
+    piv = np.zeros(max(n, 1), dtype=np.int32)
+    rank = ctypes.c_int(0)
+    st = getattr(lib, "jjo_bp_factor_" + sfx)(_ptr(Hf) if n else None, n, max(n, 1), float(tol),
+                                              _ptr(G) if n else None, _ptr(J), ctypes.byref(rank), _ptr(perm),
+                                              _ptr(piv))
+    r = rank.value
+    return dict(G=G[:, :r], J=J[:r], rank=r, perm=perm[:n], pivsize=piv[:n], status=st)

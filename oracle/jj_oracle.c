@@ -11,6 +11,9 @@
  *   jjo_solve_lz  complex, long double
  * The long double forms adjudicate differences between two correct double
  * results (their difference is bounded by eps * kappa of the column-scaled G).
+ * Each instantiation also holds the front end H -> G J G^* (jj_bp_body.inc,
+ * jjo_bp_factor_*: Bunch-Parlett factorization and the diagonalisation of its
+ * 2x2 blocks) and the rectangular solve (jjo_solve_rect_*).
  *
  * Build: gcc -O2 -fno-fast-math -ffp-contract=off -shared -fPIC (no FMA
  * contraction, no reassociation: every sum is evaluated in source order).
@@ -29,6 +32,7 @@
 #define R_FABS fabs
 #define R_HYPOT hypot
 #include "jj_oracle_body.inc"
+#include "jj_bp_body.inc"
 #undef RT
 #undef ST
 #undef IS_CPLX
@@ -46,6 +50,7 @@
 #define R_FABS fabsl
 #define R_HYPOT hypotl
 #include "jj_oracle_body.inc"
+#include "jj_bp_body.inc"
 #undef RT
 #undef ST
 #undef IS_CPLX
@@ -67,6 +72,7 @@
 #define CIMAG cimag
 #define IUNIT ((double _Complex)I)
 #include "jj_oracle_body.inc"
+#include "jj_bp_body.inc"
 #undef RT
 #undef ST
 #undef IS_CPLX
@@ -92,3 +98,4 @@
 #define CIMAG cimagl
 #define IUNIT ((long double _Complex)I)
 #include "jj_oracle_body.inc"
+#include "jj_bp_body.inc"

@@ -31,8 +31,8 @@ MUTATIONS = {
     "eigenvalue_sign_dropped": ("lam[i] = (RT)J[i] * d;", "lam[i] = d;"),
     "skips_adjacent_pairs": ("for (int s = r + 1; s < n; s++)", "for (int s = r + 2; s < n; s++)"),
     "ascending_sort": ("lam[idx[b]] < lam[key]", "lam[idx[b]] > lam[key]"),
-    "eigenvector_wrong_column": ("ST v = nrm > 0 ? G[(size_t)c * n + i] / nrm : (ST)0;",
-                                 "ST v = nrm > 0 ? G[(size_t)k * n + i] / nrm : (ST)0;"),
+    "eigenvector_wrong_column": ("ST v = nrm > 0 ? G[(size_t)c * m + i] / nrm : (ST)0;",
+                                 "ST v = nrm > 0 ? G[(size_t)k * m + i] / nrm : (ST)0;"),
     "norm_missing_imag": ("s += CREAL(x[k]) * CREAL(x[k]) + CIMAG(x[k]) * CIMAG(x[k]);",
                           "s += CREAL(x[k]) * CREAL(x[k]);"),
 }
@@ -52,7 +52,7 @@ def test_unmutated_oracle_passes_battery():
 def test_mutation_is_caught(name, tmp_path):
     old, new = MUTATIONS[name]
     src = os.path.dirname(oracle.__file__)
-    for f in ("jj_oracle.c", "jj_oracle_body.inc"):
+    for f in ("jj_oracle.c", "jj_oracle_body.inc", "jj_bp_body.inc"):
         shutil.copy(os.path.join(src, f), tmp_path / f)
     body = (tmp_path / "jj_oracle_body.inc").read_text()
     assert body.count(old) >= 1, "mutation target not found in the oracle source"
