@@ -106,13 +106,11 @@ def test_mixed_precision_batch_matches_oracle():
         check_vectors(G, J, lam, V)
 
 
-def test_full_size_batch_workload5():
-    # the 4096-matrix batch (n ~ U{16..512}, half real, half complex) in its
-    # configured form (mixed precision on), one jjacobi_solve_batched call:
-    # every member converged, its inertia equal to J's sign counts, the trace
-    # identity sum(lambda) = sum_j j_j ||g_j||^2, its prescribed spectrum within
-    # 1e-9 (measured 5e-11; G is the rounded product of the generator); six
-    # members with n <= 256 against the CPU oracle at the parity bar
+@pytest.fixture(scope="module")
+def workload5():
+    """The 4096-matrix batch (n ~ U{16..512}, half real, half complex) in its
+    configured form (mixed precision on), solved by one jjacobi_solve_batched
+    call; returns the members and the eigenvalues."""
     import paper_1008_4166_amd as jj
     specs = jjgen.batch_recipe(count=4096)
     flat, offs, Js, lams_pres = jjgen.make_batch(specs)
@@ -130,7 +128,7 @@ def test_full_size_batch_workload5():
     infos = (jj.jj_info * count)()
     worst = jj.jjacobi_solve_batched(count, dts, Gp, Js, ns, ns, Lp, Vp, ns, 0.0, 0, opts, infos)
     torch.cuda.synchronize()
-    assert worst == 0, [infos[k].status for k in range(count) if infos[k].status]
+    statuses = [infos[k].status for k in range(count)]
     lam_h = lam.cpu().numpy()
     del work, vbuf
 
@@ -140,13 +138,44 @@ def test_full_size_batch_workload5():
             g = g.view(np.complex128)
         return g.reshape(ns[k], ns[k]).T
 
-    for k in range(count):
-        lk = lam_h[loff[k]:loff[k + 1]]
-        G = member(k)
-        assert np.sum(lk > 0) == np.sum(Js[k] > 0), k
-        tr = float(np.sum(Js[k].astype(float) * np.sum(np.abs(G) ** 2, axis=0)))
+    return dict(specs=specs, ns=ns, Js=Js, lams_pres=lams_pres, worst=worst, statuses=statuses,
+                lam=[lam_h[loff[k]:loff[k + 1]] for k in range(count)], member=member)
+
+
+def test_full_size_batch_workload5(workload5):
+    # every member converged, its inertia equal to J's sign counts, the trace
+    # identity sum(lambda) = sum_j j_j ||g_j||^2, its prescribed spectrum within
+    # 1e-9 (measured 5e-11; G is the rounded product of the generator)
+    w = workload5
+    assert w["worst"] == 0, [s for s in w["statuses"] if s]
+    for k in range(len(w["ns"])):
+        lk = w["lam"][k]
+        G = w["member"](k)
+        J = w["Js"][k]
+        assert np.sum(lk > 0) == np.sum(J > 0), k
+        tr = float(np.sum(J.astype(float) * np.sum(np.abs(G) ** 2, axis=0)))
         assert abs(float(np.sum(lk)) - tr) <= 1e-12 * float(np.sum(np.abs(lk))), k
-        assert rel_err(lk, np.sort(lams_pres[k])[::-1]) <= 1e-9, k
-    small = [k for k in range(count) if ns[k] <= 256]
-    for k in [small[i] for i in np.linspace(0, len(small) - 1, 6).astype(int)]:
-        check_parity(member(k), Js[k], lam_h[loff[k]:loff[k + 1]], "batch member %d (n=%d)" % (k, ns[k]))
+        assert rel_err(lk, np.sort(w["lams_pres"][k])[::-1]) <= 1e-9, k
+
+
+def _sample(w, pred, count):
+    ks = [k for k in range(len(w["ns"])) if pred(k)]
+    return [ks[i] for i in np.linspace(0, len(ks) - 1, count).astype(int)]
+
+
+def test_batch_workload5_small_members_against_oracle(workload5):
+    # six members with n <= 256 (one or a few blocked steps) at the parity bar
+    w = workload5
+    for k in _sample(w, lambda k: w["ns"][k] <= 256, 6):
+        check_parity(w["member"](k), w["Js"][k], w["lam"][k], "batch member %d (n=%d)" % (k, w["ns"][k]))
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_batch_workload5_large_members_against_oracle(workload5, cplx):
+    # two real and two complex members with n in (400, 512]: several blocks,
+    # multi-step sweeps, slot compaction between rounds
+    w = workload5
+    ks = _sample(w, lambda k: w["ns"][k] > 400 and w["specs"][k]["cplx"] == cplx, 2)
+    for k in ks:
+        assert w["statuses"][k] == 0
+        check_parity(w["member"](k), w["Js"][k], w["lam"][k], "batch member %d (n=%d)" % (k, w["ns"][k]))
