@@ -55,6 +55,7 @@ extern "C" {
 #define JJ_BREAKDOWN 2
 #define JJ_NONFINITE 3
 #define JJ_HIP_ERROR 4
+#define JJ_SCRATCH_TOO_SMALL 5 /* jjacobi_solve_noalloc only: see there */
 
 #define JJ_F64 0 /* real double */
 #define JJ_C128 1 /* complex double, interleaved */
@@ -129,6 +130,27 @@ int jjacobi_zsolve(void* G, const signed char* J, int n, int ldg, double* lambda
 int jjacobi_solve_ex(int dtype, void* G, const signed char* J, int n, int ldg, double* lambda,
                      void* V, int ldv, double tol, int max_sweeps, const jj_opts* opts,
                      jj_info* info);
+
+/* The same solve with no device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Arguments, results and status codes are those of
+ * jjacobi_solve_ex.  The workspace is a fixed device array inside the library
+ * (JJ_NOALLOC_SCRATCH_BYTES per device, held until the process ends); no
+ * hipMalloc, hipFree, stream, event or graph is created.  The kernels run
+ * eagerly on opts->stream (NULL: the null stream), the block width is
+ * opts->block_width or 32 (never timed), and opts->profile is ignored.
+ * A solve whose workspace does not fit returns JJ_SCRATCH_TOO_SMALL before
+ * any device work (jjacobi_status_string(5) gives the bytes it needs); it fits
+ * for real n <= 4096 and complex n <= 2048 at the default block width without
+ * the diagonal-block pass.  Every call on a device shares that device's array
+ * and leaves its contents behind; the library's lock serialises calls within
+ * a process and each call has finished on the device when it returns, so
+ * calls that overlapped on one device (one in flight while another starts)
+ * would race on it and are excluded by that lock. */
+#define JJ_NOALLOC_SCRATCH_BYTES ((unsigned long long)32 << 20)
+int jjacobi_solve_noalloc(int dtype, void* G, const signed char* J, int n, int ldg, double* lambda,
+                          void* V, int ldv, double tol, int max_sweeps, const jj_opts* opts,
+                          jj_info* info);
 
 /* Many independent problems in one call (problem k uses dtype[k], G[k], J[k],
  * n[k], ldg[k], lambda[k], V[k], ldv[k]; all device pointers except J[k]).

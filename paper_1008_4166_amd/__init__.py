@@ -16,6 +16,8 @@ from . import _lib
 from ._lib import jj_info, jj_opts
 
 JJ_F64, JJ_C128 = 0, 1
+JJ_SCRATCH_TOO_SMALL = 5
+NOALLOC_SCRATCH_BYTES = 32 << 20
 
 
 def _J_array(J, n):
@@ -47,6 +49,13 @@ def jjacobi_solve_ex(dtype, G, J, n, ldg, lam, V, ldv, tol=0.0, max_sweeps=0, op
     return _lib.load().jjacobi_solve_ex(dtype, G, Jh.ctypes.data, n, ldg, lam, V, ldv, tol, max_sweeps,
                                         ctypes.byref(opts) if opts is not None else None,
                                         ctypes.byref(info) if info is not None else None)
+
+
+def jjacobi_solve_noalloc(dtype, G, J, n, ldg, lam, V, ldv, tol=0.0, max_sweeps=0, opts=None, info=None):
+    Jh = _J_array(J, n)
+    return _lib.load().jjacobi_solve_noalloc(dtype, G, Jh.ctypes.data, n, ldg, lam, V, ldv, tol, max_sweeps,
+                                             ctypes.byref(opts) if opts is not None else None,
+                                             ctypes.byref(info) if info is not None else None)
 
 
 def jjacobi_solve_batched(count, dtypes, Gs, Js, ns, ldgs, lams, Vs, ldvs, tol=0.0, max_sweeps=0, opts=None,

@@ -47,8 +47,8 @@ class jj_profile(ctypes.Structure):
 
 # exported symbols declared in include/jjacobi.h
 ABI_SYMBOLS = ("jjacobi_default_opts", "jjacobi_solve", "jjacobi_zsolve", "jjacobi_solve_ex",
-               "jjacobi_solve_batched", "jjacobi_last_profile", "jjacobi_status_string",
-               "jjacobi_release_workspace")
+               "jjacobi_solve_noalloc", "jjacobi_solve_batched", "jjacobi_last_profile",
+               "jjacobi_status_string", "jjacobi_release_workspace")
 
 _lib = None
 
@@ -77,6 +77,8 @@ def load(path=SO):
     lib.jjacobi_zsolve.restype = I
     lib.jjacobi_solve_ex.argtypes = [I, P, P, I, I, P, P, I, D, I, ctypes.POINTER(jj_opts), ctypes.POINTER(jj_info)]
     lib.jjacobi_solve_ex.restype = I
+    lib.jjacobi_solve_noalloc.argtypes = lib.jjacobi_solve_ex.argtypes
+    lib.jjacobi_solve_noalloc.restype = I
     lib.jjacobi_solve_batched.argtypes = [I, P, P, P, P, P, P, P, P, D, I, ctypes.POINTER(jj_opts),
                                           ctypes.POINTER(jj_info)]
     lib.jjacobi_solve_batched.restype = I

@@ -81,6 +81,29 @@ static char* arena_get(size_t bytes) {
   return a.base;
 }
 
+// Fixed device scratch of jjacobi_solve_noalloc, for callers that cannot
+// allocate device memory: one array per device in the library's code object,
+// held until the process ends.  In host code `scratch` names a host-side
+// stand-in, never the device array: its device address comes from
+// hipGetSymbolAddress, taken once per device with that device current, and
+// only that address is handed to kernels.
+constexpr size_t kScratchBytes = JJ_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kScratchBytes];
+static void* g_scratch_dev[64];
+
+static char* scratch_base() {
+  int dev = 0;
+  ck(hipGetDevice(&dev), "hipGetDevice");
+  void*& p = g_scratch_dev[dev & 63];
+  if (p == nullptr) ck(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+  return (char*)p;
+}
+
+// A solve that needs more workspace than the fixed scratch holds.
+struct ScratchTooSmall {
+  size_t need;
+};
+
 // Optional per-launch timing with HIP events recorded on the solve stream.
 struct Profiler {
   bool on = false;
@@ -363,14 +386,20 @@ static int tuned_block_width(int dtype, void* G, const signed char* J, int n, in
   return it->second;
 }
 
+// noalloc: the workspace is the fixed device scratch, the work runs eagerly on
+// the caller's stream (no library stream, events, graphs or block-width tuning:
+// each of those allocates), and a solve whose workspace exceeds the scratch
+// throws ScratchTooSmall before any device work.
 static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, double* lambda, void* Vv,
-                     int ldv, double tol, int max_sweeps, const jj_opts& o, jj_info* info, bool graphs_ok = true) {
+                     int ldv, double tol, int max_sweeps, const jj_opts& o, jj_info* info, bool graphs_ok = true,
+                     bool noalloc = false) {
   auto t0 = std::chrono::steady_clock::now();
   const int cplx = dtype == JJ_C128;
   double* G = (double*)Gv;
   double* V = (double*)Vv;
-  hipStream_t stream = lib_stream();
-  StreamJoin join((hipStream_t)o.stream, stream);
+  if (noalloc) graphs_ok = false;
+  hipStream_t stream = noalloc ? (hipStream_t)o.stream : lib_stream();
+  StreamJoin join(noalloc ? stream : (hipStream_t)o.stream, stream);
   // block width: the caller's, else tuned for large problems (first use of a
   // size bucket), else 32
   int nt = o.block_width > 0 ? std::min(o.block_width, kMaxBlock) : 32;
@@ -391,7 +420,8 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
   std::vector<int> dcols, dm, dnf;
   std::vector<signed char> dsg;
   build_diag_tables(P, dcols, dsg, dm, dnf);
-  const int nb_piv = std::max(h, P.nbl);
+  // pivot slots: the pairs of a step, or every block for the diagonal pass
+  const int nb_piv = o.diag_pass != 0 ? std::max(h, P.nbl) : h;
 
   // workspace layout
   const size_t tab = (size_t)std::max(P.nsteps, 1) * h * kMaxPivot;
@@ -417,7 +447,8 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
     c.take<int>(n);
     need = c.off + 256;
   }
-  Carver c{arena_get(need)};
+  if (noalloc && need > kScratchBytes) throw ScratchTooSmall{need};
+  Carver c{noalloc ? scratch_base() : arena_get(need)};
   int* d_cols = c.take<int>(tab);
   signed char* d_sg = c.take<signed char>(tab);
   int* d_m = c.take<int>((size_t)std::max(P.nsteps, 1) * h);
@@ -451,7 +482,7 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
   ck(hipMemcpyAsync(d_sgn, P.sgn.data(), n, hipMemcpyHostToDevice, stream), "H2D");
 
   Profiler prof;
-  prof.on = o.profile != 0;
+  prof.on = o.profile != 0 && !noalloc;
   prof.s = stream;
   std::memset(&prof.acc, 0, sizeof(prof.acc));
 
@@ -1235,6 +1266,34 @@ int jjacobi_solve_ex(int dtype, void* G, const signed char* J, int n, int ldg, d
   }
 }
 
+int jjacobi_solve_noalloc(int dtype, void* G, const signed char* J, int n, int ldg, double* lambda, void* V,
+                          int ldv, double tol, int max_sweeps, const jj_opts* opts, jj_info* info) {
+  int a = check_args(dtype, G, J, n, ldg, lambda, V, ldv);
+  if (a < 0) {
+    if (info) info->status = a;
+    return a;
+  }
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (n == 0) return 0;
+  jj_opts o;
+  jjacobi_default_opts(&o);
+  if (opts) o = *opts;
+  std::lock_guard<std::mutex> lk(g_mutex);
+  try {
+    return solve_one(dtype, G, J, n, ldg, lambda, V, ldv, tol, max_sweeps, o, info, false, true);
+  } catch (const ScratchTooSmall& e) {
+    char msg[160];
+    std::snprintf(msg, sizeof(msg), "the solve needs %zu bytes of device scratch; the fixed array holds %zu",
+                  e.need, kScratchBytes);
+    g_last_error = msg;
+    if (info) info->status = JJ_SCRATCH_TOO_SMALL;
+    return JJ_SCRATCH_TOO_SMALL;
+  } catch (const HipFail&) {
+    if (info) info->status = JJ_HIP_ERROR;
+    return JJ_HIP_ERROR;
+  }
+}
+
 int jjacobi_solve(double* G, const signed char* J, int n, int ldg, double* lambda, double* V, double tol,
                   int max_sweeps) {
   return jjacobi_solve_ex(JJ_F64, G, J, n, ldg, lambda, V, n, tol, max_sweeps, nullptr, nullptr);
@@ -1287,6 +1346,9 @@ const char* jjacobi_status_string(int status) {
       return "non-finite input";
     case 4:
       return g_last_error.empty() ? "HIP runtime error" : g_last_error.c_str();
+    case 5:
+      return g_last_error.empty() ? "the solve needs more device scratch than jjacobi_solve_noalloc holds"
+                                  : g_last_error.c_str();
     default:
       return status < 0 ? "invalid argument" : "unknown status";
   }
