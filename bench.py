@@ -127,26 +127,87 @@ def roofline(prof, n, cplx):
     return r, work
 
 
-def cpu_baseline(n_full, sweeps_full):
-    """The oracle, single-threaded, on a bounded sample: one row-cyclic sweep on
-    the n = 2048 instance of the same workload law, scaled by n^3 to n = 4096 and
-    by the oracle's sweep count on the full input."""
+def host_cpu():
+    """CPU model and thread counts of the host the oracle runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return dict(model=model, logical_cpus=os.cpu_count(), usable_cpus=len(os.sched_getaffinity(0)))
+
+
+def cpu_baseline(n_full, sweeps_full, batch_every=16, batch_procs=16):
+    """The oracle as it stands on the host cores, on bounded samples.
+
+    Single solves: one full oracle solve (every sweep, single-threaded) of the
+    n = 1024 instance of the same workload law, measured; `value` scales it to
+    n = 4096 by n^3 and by the ratio of the oracle's sweep counts (41 on the
+    n = 4096 input, stored with its eigenvalues), labelled extrapolated.
+    Batched: the oracle over a process pool (the members are independent) on
+    every `batch_every`-th member of the 4096-matrix batch, scaled to mats/s."""
     import jjgen
     import oracle
-    ns = 2048
+    ns = 1024
     G, J, _ = jjgen.config(WORKLOAD, n=ns)
     t = time.perf_counter()
-    r = oracle.solve(G, J, max_sweeps=1, vectors=False)
+    r = oracle.solve(G, J, vectors=False)
     dt = time.perf_counter() - t
-    t_full = dt * (n_full / ns) ** 3 * sweeps_full
+    t_full = dt * (n_full / ns) ** 3 * sweeps_full / max(1, r["sweeps"])
     G1, J1, _ = jjgen.config(1)
     t1 = time.perf_counter()
     oracle.solve(G1, J1, vectors=False)
     dt1 = time.perf_counter() - t1
-    return dict(value=n_full / t_full, unit="eigenpairs/s", cores=1, kind="oracle", workload1_seconds=dt1,
-                sample="one oracle sweep on the n=%d instance of the workload (%.1f s), scaled by (4096/%d)^3 "
-                       "and by the oracle's %d sweeps on the n=4096 input" % (ns, dt, ns, sweeps_full),
-                sweep_seconds_sample=dt, status_sample=r["status"])
+    out = dict(value=n_full / t_full, unit="eigenpairs/s", cores=1, kind="oracle", host=host_cpu(),
+               extrapolated=True,
+               sample="one full single-threaded oracle solve (all %d sweeps) of the n=%d instance of the workload "
+                      "law, %.1f s measured; value scaled to n=%d by (%d/%d)^3 and by the oracle's %d sweeps on "
+                      "the n=%d input" % (r["sweeps"], ns, dt, n_full, n_full, ns, sweeps_full, n_full),
+               measured=dict(n=ns, seconds=dt, sweeps=r["sweeps"], status=r["status"], eigenpairs_per_s=ns / dt),
+               workload1_seconds=dt1)
+    out["batched"] = cpu_baseline_batched(batch_every, batch_procs)
+    return out
+
+
+_BATCH_SAMPLE = []
+
+
+def _oracle_member(k):
+    import oracle
+    G, J = _BATCH_SAMPLE[k]
+    t = time.perf_counter()
+    r = oracle.solve(G, J, vectors=False)
+    return time.perf_counter() - t, r["status"]
+
+
+def cpu_baseline_batched(every, procs):
+    """The oracle over `procs` worker processes on every `every`-th member of
+    the batched workload; mats/s = members / wall time of the pool."""
+    import multiprocessing as mp
+
+    import jjgen
+    specs = jjgen.batch_recipe(count=4096)[::every]
+    procs = max(1, min(procs, len(os.sched_getaffinity(0))))
+    _BATCH_SAMPLE.clear()
+    for sp in specs:
+        G, J, _ = jjgen.batch_member(sp)
+        _BATCH_SAMPLE.append((G, J))
+    with mp.get_context("fork").Pool(procs) as pool:
+        t = time.perf_counter()
+        res = pool.map(_oracle_member, range(len(specs)), chunksize=1)
+        wall = time.perf_counter() - t
+    _BATCH_SAMPLE.clear()
+    return dict(value=len(specs) / wall, unit="mats/s", cores=procs, kind="oracle",
+                sample="%d members (every %d-th of the 4096-matrix batch, %d real / %d complex), one oracle solve "
+                       "each over a pool of %d processes, %.1f s wall" % (
+                           len(specs), every, sum(not s["cplx"] for s in specs), sum(s["cplx"] for s in specs),
+                           procs, wall),
+                seconds=wall, cpu_seconds=float(sum(x[0] for x in res)),
+                statuses={str(v): [x[1] for x in res].count(v) for v in set(x[1] for x in res)})
 
 
 def bench_batched(jj, torch, count, loop_sample):
@@ -334,8 +395,85 @@ def bench_config4(jj, torch, steps):
     a, b = res["complex128"].pop("lam"), res["mixed"].pop("lam")
     res["mixed"]["vs_complex128_max_rel"] = float(np.max(np.abs(a - b) / np.abs(a)))
     res["mixed"]["speedup_vs_complex128"] = res["complex128"]["seconds"] / res["mixed"]["seconds"]
+    # complex128 per block width: whole solves at 32 and 64 (three-level pivots),
+    # three sweeps at 16
+    per = {}
+    for bw, cap in ((32, 0), (64, 0), (16, 3)):
+        o = jj.make_opts(stream=stream, block_width=bw)
+        Gw = pristine.clone()
+        info = jj.jj_info()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = jj.jjacobi_solve_ex(jj.JJ_C128, Gw.data_ptr(), J, n, n, lam.data_ptr(), Vt.data_ptr(), n, 0.0, cap, o,
+                                 info)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        del Gw
+        row = dict(seconds=dt, sweeps=info.sweeps, ms_per_sweep=1e3 * dt / max(1, info.sweeps), status=st,
+                   whole_solve=cap == 0)
+        if cap == 0:
+            lh = lam.cpu().numpy()
+            row["vs_prescribed_max_rel"] = float(np.max(np.abs(lh - ref) / np.abs(ref)))
+            row["vs_complex128_default_max_rel"] = float(np.max(np.abs(lh - a) / np.abs(a)))
+        per[str(bw)] = row
+        note("n=8192 complex128 block width %d: %.2f s, %d sweeps" % (bw, dt, info.sweeps))
+    res["per_block_width"] = per
     return dict(workload="n=8192 complex Hermitian, J with 4096 positive, |lambda| log-uniform [1e-8, 1e2]",
                 steps=steps, gen_seconds=gen_s, **res)
+
+
+def bench_inner_modes(jj, torch, ks=(3, 2)):
+    """The two pivot variants side by side on workloads 3 and 2: block-oriented
+    (one inner pass over each pivot's off-diagonal block per step, Section 3.4;
+    the default) and full pivot diagonalisation (inner sweeps until no rotation,
+    Section 3.3).  Per variant: one graph-replayed solve (time, sweeps) after a
+    warm-up, and one profiled solve for the per-kernel times and the roofline
+    of its dominant kernel."""
+    import jjgen
+    out = {}
+    for k in ks:
+        G, J, lam_pres = jjgen.config(k)
+        n = G.shape[0]
+        cplx = np.iscomplexobj(G)
+        dev = torch.device("cuda:0")
+        pristine = torch.from_numpy(np.ascontiguousarray(G.T)).to(dev)
+        lam = torch.empty(n, dtype=torch.float64, device=dev)
+        Vt = torch.empty((n, n), dtype=pristine.dtype, device=dev)
+        stream = torch.cuda.current_stream().cuda_stream
+        ref = np.sort(lam_pres)[::-1]
+        res = {}
+        for name, mode in (("block_oriented", 0), ("full", 1)):
+            row = {}
+            for profiled in (False, False, True):
+                o = jj.make_opts(stream=stream, block_width=32, inner_mode=mode, profile=1 if profiled else 0)
+                Gw = pristine.clone()
+                info = jj.jj_info()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st = jj.jjacobi_solve_ex(jj.JJ_C128 if cplx else jj.JJ_F64, Gw.data_ptr(), J, n, n, lam.data_ptr(),
+                                         Vt.data_ptr(), n, 0.0, 0, o, info)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                if st != 0:
+                    raise RuntimeError("workload %d inner_mode %d: status %d" % (k, mode, st))
+                if profiled:
+                    pr = jj.jjacobi_last_profile()
+                    rf, wk = roofline(pr, n, cplx)
+                    row["roofline"] = rf
+                    row["kernel_ms_per_solve"] = {kk: pr[kk]["ms"] for kk in ("gram", "pivot", "update", "final")}
+                    row["inner_sweeps"] = pr["inner_sweeps"]
+                    row["rotations"] = pr["rotations"]
+                else:
+                    row["seconds"] = dt  # the second unprofiled solve is kept (the first is a warm-up)
+                    row["sweeps"] = info.sweeps
+            lh = lam.cpu().numpy()
+            row["vs_prescribed_max_rel"] = float(np.max(np.abs(lh - ref) / np.abs(ref)))
+            row["ms_per_sweep"] = 1e3 * row["seconds"] / max(1, row["sweeps"])
+            res[name] = row
+            note("workload %d %s: %.1f ms, %d sweeps" % (k, name, 1e3 * row["seconds"], row["sweeps"]))
+        res["full_over_block_oriented_time"] = res["full"]["seconds"] / res["block_oriented"]["seconds"]
+        out["config%d" % k] = res
+    return out
 
 
 def stored_long_oracle(k):
@@ -374,6 +512,7 @@ def main():
     ap.add_argument("--no-c4", action="store_true", help="skip the n=8192 complex leg")
     ap.add_argument("--no-small", action="store_true", help="skip the n=64 and n=1024 legs")
     ap.add_argument("--c4-steps", type=int, default=1)
+    ap.add_argument("--no-inner-modes", action="store_true", help="skip the pivot-variant comparison")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="before the timed region, one device copy of this many MiB (a reference for "
                          "hardware byte counters)")
@@ -516,6 +655,9 @@ def main():
         note("workloads 1 and 2")
         out["config1"] = bench_small(jj, torch, 1, 20)
         out["config2"] = bench_small(jj, torch, 2, 5)
+    if not args.no_inner_modes:
+        note("pivot variants (block-oriented / full) on workloads 3 and 2")
+        out["inner_modes"] = bench_inner_modes(jj, torch)
     if not args.no_batched:
         note("batched leg")
         out["batched"] = bench_batched(jj, torch, args.batch_count, args.loop_sample)
@@ -524,7 +666,7 @@ def main():
         del work
         out["config4"] = bench_config4(jj, torch, args.c4_steps)
     if not args.no_cpu:
-        note("cpu baseline (oracle sample)")
+        note("cpu baseline (oracle samples)")
         out["cpu_baseline"] = cpu_baseline(n, oracle_sweeps if oracle_sweeps else 14)
     print(json.dumps(out), flush=True)
 

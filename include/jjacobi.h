@@ -109,7 +109,8 @@ typedef struct jj_info {
   int mixed_sweeps;        /* sweeps that used the FP32 Gram (precision 1) */
   int mixed_resolved;      /* pivot solves of those sweeps redone from an FP64 Gram block
                               because the FP32 block could not be factored */
-  int reserved[6];
+  int rank;                /* jjacobi_eigh: rank of H found by the front end */
+  int reserved[5];
 } jj_info;
 
 /* Fill *opts with the defaults. */
@@ -151,6 +152,49 @@ int jjacobi_solve_ex(int dtype, void* G, const signed char* J, int n, int ldg, d
 int jjacobi_solve_noalloc(int dtype, void* G, const signed char* J, int n, int ldg, double* lambda,
                           void* V, int ldv, double tol, int max_sweeps, const jj_opts* opts,
                           jj_info* info);
+
+/* Rectangular factor (Section 2.2, last paragraphs): G has m >= n rows and n
+ * columns of full column rank, e.g. the factor of a singular H = G J G^* of
+ * rank n and order m.  lambda receives the n nonzero eigenvalues of H
+ * (descending), V (m x n, leading dimension ldv >= m) their unit eigenvectors,
+ * the columns of U~ in G W = U~ Sigma (the HSVD of G).  ldg >= m.  tol <= 0
+ * selects m * 2^-53.  Otherwise as jjacobi_solve_ex (argument k of this
+ * signature for status -k).  m = n is the square solve. */
+int jjacobi_solve_rect(int dtype, void* G, const signed char* J, int m, int n, int ldg, double* lambda,
+                       void* V, int ldv, double tol, int max_sweeps, const jj_opts* opts, jj_info* info);
+
+/* Front end (Section 2.2, eq. 2.5): the factor G and signs J of a Hermitian
+ * H = G J G^*, by the Bunch-Parlett factorization P H P^T = M D M^* with
+ * complete pivoting (Bunch and Parlett 1971: 1x1 pivot on the largest diagonal
+ * entry when it is at least alpha = (1 + sqrt 17)/8 times the largest entry of
+ * the trailing matrix, otherwise a 2x2 pivot on the largest entry), then
+ * D's 2x2 blocks diagonalised by one rotation each and M's columns scaled:
+ * G = P^T M Q |Lambda|^{1/2}, J = sign(Lambda).  G is lower block triangular
+ * up to the row permutation.
+ *   H     device, n x n, leading dimension ldh; only the lower triangle is read
+ *         (complex: the imaginary parts of the diagonal are ignored); not modified.
+ *   G     device out, n x n, leading dimension ldg >= n: the first *rank
+ *         columns receive G, the others are zeroed.
+ *   J     host out, n signed chars: the first *rank are the signs, the rest 0.
+ *   rank  host out: r.  The factorization stops when every entry of the
+ *         trailing matrix is at most tol * max|h_ij| (tol <= 0: n * 2^-53); H
+ *         then has rank r and G is n x r of full column rank.
+ * Runs on opts->stream (nullable opts); returns after completion.  Returns 0,
+ * JJ_NONFINITE (3) for a non-finite entry in the lower triangle, JJ_HIP_ERROR,
+ * or -k for an invalid k-th argument. */
+int jjacobi_factor(int dtype, const void* H, int n, int ldh, void* G, int ldg, signed char* J, int* rank,
+                   double tol, const jj_opts* opts);
+
+/* Eigenpairs of a Hermitian H given explicitly: jjacobi_factor (default rank
+ * tolerance) followed by jjacobi_solve_rect on the n x r factor.  H (device,
+ * n x n, ldh, lower triangle read) is destroyed: G is formed in its storage.
+ * lambda (n doubles): the r nonzero eigenvalues descending, then n - r zeros;
+ * V (n x n, ldv >= n): their unit eigenvectors, then n - r zero columns (the
+ * null space of a singular H is not formed).  info->rank receives r.  tol and
+ * max_sweeps as for the solve.  Status codes as jjacobi_solve_ex (argument k of
+ * this signature for -k). */
+int jjacobi_eigh(int dtype, void* H, int n, int ldh, double* lambda, void* V, int ldv, double tol,
+                 int max_sweeps, const jj_opts* opts, jj_info* info);
 
 /* Many independent problems in one call (problem k uses dtype[k], G[k], J[k],
  * n[k], ldg[k], lambda[k], V[k], ldv[k]; all device pointers except J[k]).

@@ -58,6 +58,28 @@ def jjacobi_solve_noalloc(dtype, G, J, n, ldg, lam, V, ldv, tol=0.0, max_sweeps=
                                              ctypes.byref(info) if info is not None else None)
 
 
+def jjacobi_solve_rect(dtype, G, J, m, n, ldg, lam, V, ldv, tol=0.0, max_sweeps=0, opts=None, info=None):
+    Jh = _J_array(J, n)
+    return _lib.load().jjacobi_solve_rect(dtype, G, Jh.ctypes.data, m, n, ldg, lam, V, ldv, tol, max_sweeps,
+                                          ctypes.byref(opts) if opts is not None else None,
+                                          ctypes.byref(info) if info is not None else None)
+
+
+def jjacobi_factor(dtype, H, n, ldh, G, ldg, tol=0.0, opts=None):
+    """Returns (status, J (n int8; the first rank entries are the signs), rank)."""
+    J = np.zeros(max(n, 1), dtype=np.int8)
+    rank = ctypes.c_int(0)
+    st = _lib.load().jjacobi_factor(dtype, H, n, ldh, G, ldg, J.ctypes.data, ctypes.byref(rank), tol,
+                                    ctypes.byref(opts) if opts is not None else None)
+    return st, J[:n], rank.value
+
+
+def jjacobi_eigh(dtype, H, n, ldh, lam, V, ldv, tol=0.0, max_sweeps=0, opts=None, info=None):
+    return _lib.load().jjacobi_eigh(dtype, H, n, ldh, lam, V, ldv, tol, max_sweeps,
+                                    ctypes.byref(opts) if opts is not None else None,
+                                    ctypes.byref(info) if info is not None else None)
+
+
 def jjacobi_solve_batched(count, dtypes, Gs, Js, ns, ldgs, lams, Vs, ldvs, tol=0.0, max_sweeps=0, opts=None,
                           infos=None):
     Jh = [_J_array(J, n) for J, n in zip(Js, ns)]
@@ -149,3 +171,67 @@ def solve_batched(Gs, Js, tol=0.0, max_sweeps=0, **opts):
     if st < 0 or st == 4:
         raise RuntimeError("jjacobi_solve_batched: %d (%s)" % (st, jjacobi_status_string(st)))
     return lams, [v.t() for v in Vts], [infos[k].as_dict() for k in range(count)], st
+
+
+def _colmajor(X):
+    """Column-major device copy of a 2-D tensor (rows of the result are its columns)."""
+    return X.t().contiguous()
+
+
+def solve_rect(G, J, tol=0.0, max_sweeps=0, **opts):
+    """Nonzero eigenpairs of H = G J G^* for a CUDA tensor G of m x n, m >= n,
+    full column rank (float64 or complex128).  Returns (lam (n,), V (m, n), info)."""
+    import torch
+    m, n = G.shape
+    cplx = G.dtype == torch.complex128
+    if not cplx and G.dtype != torch.float64:
+        raise ValueError("G must be float64 or complex128")
+    Gc = _colmajor(G)
+    lam = torch.empty(n, dtype=torch.float64, device=G.device)
+    Vt = torch.empty((n, m), dtype=G.dtype, device=G.device)
+    o = make_opts(stream=_current_stream(), **opts)
+    info = jj_info()
+    st = jjacobi_solve_rect(JJ_C128 if cplx else JJ_F64, Gc.data_ptr(), J, m, n, max(m, 1), lam.data_ptr(),
+                            Vt.data_ptr(), max(m, 1), tol, max_sweeps, o, info)
+    d = info.as_dict()
+    d["status"] = st
+    if st < 0 or st == 4:
+        raise RuntimeError("jjacobi_solve_rect: %d (%s)" % (st, jjacobi_status_string(st)))
+    return lam, Vt.t(), d
+
+
+def factor(H, tol=0.0, **opts):
+    """Front end: (G (n, r) CUDA tensor, J (r,) int8 numpy, status) with H = G J G^*."""
+    import torch
+    n = H.shape[0]
+    cplx = H.dtype == torch.complex128
+    Hc = _colmajor(H)
+    Gt = torch.empty((n, n), dtype=H.dtype, device=H.device)
+    o = make_opts(stream=_current_stream(), **opts)
+    st, J, r = jjacobi_factor(JJ_C128 if cplx else JJ_F64, Hc.data_ptr(), n, max(n, 1), Gt.data_ptr(), max(n, 1),
+                              tol, o)
+    if st < 0 or st == 4:
+        raise RuntimeError("jjacobi_factor: %d (%s)" % (st, jjacobi_status_string(st)))
+    return Gt.t()[:, :r], J[:r].copy(), st
+
+
+def eigh(H, tol=0.0, max_sweeps=0, **opts):
+    """Eigenpairs of a Hermitian CUDA tensor H (n x n) through the front end and
+    the one-sided J-Jacobi solve.  Returns (lam (n,), V (n, n), info); info['rank']
+    is the rank found (the last n - rank eigenvalues are zero, their vectors are
+    zero columns)."""
+    import torch
+    n = H.shape[0]
+    cplx = H.dtype == torch.complex128
+    Hc = _colmajor(H)
+    lam = torch.empty(n, dtype=torch.float64, device=H.device)
+    Vt = torch.empty((n, n), dtype=H.dtype, device=H.device)
+    o = make_opts(stream=_current_stream(), **opts)
+    info = jj_info()
+    st = jjacobi_eigh(JJ_C128 if cplx else JJ_F64, Hc.data_ptr(), n, max(n, 1), lam.data_ptr(), Vt.data_ptr(),
+                      max(n, 1), tol, max_sweeps, o, info)
+    d = info.as_dict()
+    d["status"] = st
+    if st < 0 or st == 4:
+        raise RuntimeError("jjacobi_eigh: %d (%s)" % (st, jjacobi_status_string(st)))
+    return lam, Vt.t(), d

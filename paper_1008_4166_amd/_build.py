@@ -5,7 +5,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SO = os.path.join(HERE, "libjjacobi.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("jj_kernels.hip", "jj_pivot.hip", "jj_batched.hip", "jj_solver.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("jj_kernels.hip", "jj_pivot.hip", "jj_batched.hip", "jj_frontend.hip",
+                                                                   "jj_three.hip", "jj_solver.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

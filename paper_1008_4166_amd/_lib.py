@@ -22,7 +22,7 @@ class jj_info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("sweeps", ctypes.c_int), ("block_width", ctypes.c_int),
                 ("nblocks", ctypes.c_int), ("pivots_rotated", ctypes.c_longlong), ("final_offdiag", ctypes.c_double),
                 ("seconds", ctypes.c_double), ("mixed_sweeps", ctypes.c_int), ("mixed_resolved", ctypes.c_int),
-                ("reserved", ctypes.c_int * 6)]
+                ("rank", ctypes.c_int), ("reserved", ctypes.c_int * 5)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -47,8 +47,9 @@ class jj_profile(ctypes.Structure):
 
 # exported symbols declared in include/jjacobi.h
 ABI_SYMBOLS = ("jjacobi_default_opts", "jjacobi_solve", "jjacobi_zsolve", "jjacobi_solve_ex",
-               "jjacobi_solve_noalloc", "jjacobi_solve_batched", "jjacobi_last_profile",
-               "jjacobi_status_string", "jjacobi_release_workspace")
+               "jjacobi_solve_noalloc", "jjacobi_solve_rect", "jjacobi_factor", "jjacobi_eigh",
+               "jjacobi_solve_batched", "jjacobi_last_profile", "jjacobi_status_string",
+               "jjacobi_release_workspace")
 
 _lib = None
 
@@ -79,6 +80,13 @@ def load(path=SO):
     lib.jjacobi_solve_ex.restype = I
     lib.jjacobi_solve_noalloc.argtypes = lib.jjacobi_solve_ex.argtypes
     lib.jjacobi_solve_noalloc.restype = I
+    lib.jjacobi_solve_rect.argtypes = [I, P, P, I, I, I, P, P, I, D, I, ctypes.POINTER(jj_opts),
+                                       ctypes.POINTER(jj_info)]
+    lib.jjacobi_solve_rect.restype = I
+    lib.jjacobi_factor.argtypes = [I, P, I, I, P, I, P, ctypes.POINTER(I), D, ctypes.POINTER(jj_opts)]
+    lib.jjacobi_factor.restype = I
+    lib.jjacobi_eigh.argtypes = [I, P, I, I, P, P, I, D, I, ctypes.POINTER(jj_opts), ctypes.POINTER(jj_info)]
+    lib.jjacobi_eigh.restype = I
     lib.jjacobi_solve_batched.argtypes = [I, P, P, P, P, P, P, P, P, D, I, ctypes.POINTER(jj_opts),
                                           ctypes.POINTER(jj_info)]
     lib.jjacobi_solve_batched.restype = I

@@ -9,8 +9,11 @@ namespace jj {
 
 // Largest pivot block (two block-columns of at most 32 columns each).
 constexpr int kMaxPivot = 64;
-// Largest block width.
+// Largest block width of a two-level pivot (a pair of blocks solved in LDS).
 constexpr int kMaxBlock = kMaxPivot / 2;
+// Largest three-level pivot (block width 64): its Cholesky factor R occupies a
+// kMaxPivot3 x kMaxPivot3 slot of the R workspace.
+constexpr int kMaxPivot3 = 2 * kMaxPivot;
 // Largest number of row chunks of one Gram block (partials summed by the pivot solver).
 constexpr int kMaxChunks = 8;
 
@@ -162,19 +165,21 @@ void launch_gram_c64mix(const double* G, int ldg, int n, const PivotList& pl, in
 // soft = 1 (mixed-precision sweeps): a pivot whose Gram block cannot be factored
 // is left untouched and counted in soft_fail instead of raising breakdown.
 // mode: 0 full inner sweeps (inner_max), 1 off-diagonal pass only, 2 (batched
-// block-oriented) full pass at step 0 of the problem's sweep, else off-diagonal.
+// block-oriented) full pass at step 0 of the problem's sweep, else off-diagonal,
+// 3 direct: a single pivot holding every column of a G of n <= kMaxPivot rows is
+// solved on G itself (no Gram block, no Cholesky; part is not read) with up to
+// inner_max inner sweeps, and the rotated columns are written back to G (G, ldg;
+// rotflag 0, pivots_rotated counts the pivot if its last inner sweep rotated).
 // Only the first ceil(n / rows_per_chunk) partials of a pivot are summed.
 // refine (nullable, single problems): refine[p] is set to 1 for a pivot that
 // failed softly and to 0 otherwise.  only (nullable): pivots with only[p] == 0
 // return at once (a re-solve of the flagged pivots).
 void launch_pivot_f64(const double* part, int nch, int n, int rows_per_chunk, const PivotList& pl, double tol,
                       int inner_max, int inner_mode, int soft, double* W, int* rotflag, SweepStats* st,
-                      hipStream_t stream, const Batch& b = Batch(), int* refine = nullptr,
-                      const int* only = nullptr);
+                      hipStream_t stream, const Batch& b, int* refine, const int* only, double* G, int ldg);
 void launch_pivot_c128(const double* part, int nch, int n, int rows_per_chunk, const PivotList& pl, double tol,
                        int inner_max, int inner_mode, int soft, double* W, int* rotflag, SweepStats* st,
-                       hipStream_t stream, const Batch& b = Batch(), int* refine = nullptr,
-                       const int* only = nullptr);
+                       hipStream_t stream, const Batch& b, int* refine, const int* only, double* G, int ldg);
 
 // [G_i G_j] <- [G_i G_j] W_P in place for pivots with rotflag set.
 // nch_u: number of row chunks in the grid (0: ceil(n / rows_per_chunk)).
@@ -199,12 +204,53 @@ void launch_batch_finalize(int count, double* const* gptr, const int* ldg, const
                            hipStream_t stream);
 
 void launch_reset_stats(SweepStats* st, hipStream_t stream);
-void launch_check_finite(const double* G, int ldg, int n, int cplx, SweepStats* st, hipStream_t stream);
+// G has `rows` rows and `cols` columns (rows >= cols).
+void launch_check_finite(const double* G, int ldg, int rows, int cols, int cplx, SweepStats* st, hipStream_t stream);
 
-// Finalisation: d[q] = ||G[:, colmap[q]]||^2; lam = sg*d; rank by (lam desc, colmap asc);
-// lambda[rank[q]] = lam[q], V[:, rank[q]] = G[:, colmap[q]] / sqrt(d[q]).
-void launch_finalize(const double* G, int ldg, int n, int cplx, const int* colmap, const signed char* sgn,
-                     double* d, int* rank, double* lambda, double* V, int ldv, SweepStats* st,
-                     hipStream_t stream);
+// Finalisation over the cols columns of G (rows rows each): d[q] = ||G[:, colmap[q]]||^2;
+// lam = sg*d; rank by (lam desc, colmap asc); lambda[rank[q]] = lam[q],
+// V[:, rank[q]] = G[:, colmap[q]] / sqrt(d[q]).
+void launch_finalize(const double* G, int ldg, int rows, int cols, int cplx, const int* colmap,
+                     const signed char* sgn, double* d, int* rank, double* lambda, double* V, int ldv,
+                     SweepStats* st, hipStream_t stream);
+
+// ---- three-level pivots (block width 64; jj_three.hip) ----
+// Sum the partials of each pair's six 64-column sub-pivots (I, J, I1 J1, I1 J2,
+// I2 J1, I2 J2) into A_P (order n1s[p] + n2s[p] <= 128), record the scaled
+// off-diagonal of the part a step annihilates (all of A_P if first, else A_IJ),
+// factor A_P = R^* R and write R to R + p * 128 * ldr (128 x 128, zero-padded).
+void launch_chol128(bool cplx, const double* part, int nch, int nrows, int rows_per_chunk, const int* n1s,
+                    const int* n2s, int count, double* R, int ldr, int first, SweepStats* st, hipStream_t stream);
+
+// ---- front end H -> G J G^* (Bunch-Parlett; jj_frontend.hip) ----
+constexpr int kBpThreads = 256;  // threads of every front-end workgroup (update tiles: 256 rows x 8 columns)
+constexpr int kBpGroups = 1024;  // workgroups of one update launch (and partial maxima per step)
+
+struct BPState {
+  int k;          // next column to factor
+  int done;       // 1 once the trailing matrix is negligible (or k = n, or non-finite input)
+  int kcur, s;    // column and order (1, 2; 0: none) of the pivot the next update applies
+  int rank;       // columns factored, set when done
+  int nonfinite;  // a non-finite entry was met
+  double hmax;    // max |h_ij| of the input
+};
+struct BPPartial {
+  double mu0;      // largest |s_ij| of a workgroup's entries
+  long long idx0;  // its column-major index j * n + i (smallest among equals)
+  double mu1;      // largest |s_ii| of its diagonal entries
+  long long idx1;  // its row index
+};
+
+void launch_bp_init(BPState* st, int* perm, int n, hipStream_t stream);
+// Schur update of the pivot recorded in st (none at the start: a scan), fused
+// with the per-workgroup maxima of the new trailing lower triangle.
+void launch_bp_update(double* A, int n, int cplx, const double* pcol, BPState* st, BPPartial* part,
+                      hipStream_t stream);
+// Pivot choice, symmetric interchanges, column(s) of M; pcol receives the unscaled pivot columns.
+void launch_bp_select(double* A, int n, int cplx, double tol, double* pcol, BPState* st, const BPPartial* part,
+                      int* perm, int* piv, double* dblk, hipStream_t stream);
+// G = P^T M Q |Lambda|^{1/2} (first st->rank columns; the others zeroed) and J.
+void launch_bp_build_g(const double* A, int n, int cplx, const BPState* st, const int* perm, const int* piv,
+                       const double* dblk, double* G, int ldg, signed char* J, hipStream_t stream);
 
 }  // namespace jj

@@ -573,23 +573,23 @@ __global__ void k_reset_stats(SweepStats* st) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_check_finite(const double* __restrict__ G, int ldg, int n, int w,
+__global__ __launch_bounds__(256) void k_check_finite(const double* __restrict__ G, int ldg, int rows, int w,
                                                       SweepStats* st) {
   const int col = blockIdx.x;
   const double* c = G + (size_t)col * ldg * w;
   int bad = 0;
-  for (int i = threadIdx.x; i < n * w; i += 256) bad |= !isfinite(c[i]);
+  for (int i = threadIdx.x; i < rows * w; i += 256) bad |= !isfinite(c[i]);
   if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(&st->nonfinite, 1);
 }
 
 // d[q] = ||G[:, colmap[q]]||^2 ; one block per column, fixed-order tree reduction
-__global__ __launch_bounds__(256) void k_colnorm(const double* __restrict__ G, int ldg, int n, int w,
+__global__ __launch_bounds__(256) void k_colnorm(const double* __restrict__ G, int ldg, int rows, int w,
                                                  const int* __restrict__ colmap, double* __restrict__ d) {
   __shared__ double red[256];
   const int q = blockIdx.x, tid = threadIdx.x;
   const double* c = G + (size_t)colmap[q] * ldg * w;
   double s = 0.0;
-  for (int i = tid; i < n * w; i += 256) s += c[i] * c[i];
+  for (int i = tid; i < rows * w; i += 256) s += c[i] * c[i];
   red[tid] = s;
   __syncthreads();
   for (int k = 128; k > 0; k >>= 1) {
@@ -626,7 +626,7 @@ __global__ __launch_bounds__(256) void k_rank(int n, const double* __restrict__ 
 }
 
 // V[:, rank[q]] = G[:, colmap[q]] / sqrt(d[q]) ; one block per column
-__global__ __launch_bounds__(256) void k_write_v(const double* __restrict__ G, int ldg, int n, int w,
+__global__ __launch_bounds__(256) void k_write_v(const double* __restrict__ G, int ldg, int rows, int w,
                                                  const int* __restrict__ colmap, const double* __restrict__ d,
                                                  const int* __restrict__ rank, double* __restrict__ V, int ldv) {
   const int q = blockIdx.x;
@@ -634,7 +634,7 @@ __global__ __launch_bounds__(256) void k_write_v(const double* __restrict__ G, i
   double* o = V + (size_t)rank[q] * ldv * w;
   const double dq = d[q];
   const double inv = dq > 0.0 ? 1.0 / sqrt(dq) : 0.0;
-  for (int i = threadIdx.x; i < n * w; i += 256) o[i] = c[i] * inv;
+  for (int i = threadIdx.x; i < rows * w; i += 256) o[i] = c[i] * inv;
 }
 
 // ---------------------------------------------------------------------------
@@ -682,17 +682,18 @@ void launch_reset_stats(SweepStats* st, hipStream_t stream) {
   launch(k_reset_stats, dim3(1), dim3(64), 0, stream, st);
 }
 
-void launch_check_finite(const double* G, int ldg, int n, int cplx, SweepStats* st, hipStream_t stream) {
-  launch(k_check_finite, dim3(n), dim3(256), 0, stream, G, ldg, n, cplx ? 2 : 1, st);
+void launch_check_finite(const double* G, int ldg, int rows, int cols, int cplx, SweepStats* st,
+                         hipStream_t stream) {
+  launch(k_check_finite, dim3(cols), dim3(256), 0, stream, G, ldg, rows, cplx ? 2 : 1, st);
 }
 
-void launch_finalize(const double* G, int ldg, int n, int cplx, const int* colmap, const signed char* sgn,
-                     double* d, int* rank, double* lambda, double* V, int ldv, SweepStats* st,
-                     hipStream_t stream) {
+void launch_finalize(const double* G, int ldg, int rows, int cols, int cplx, const int* colmap,
+                     const signed char* sgn, double* d, int* rank, double* lambda, double* V, int ldv,
+                     SweepStats* st, hipStream_t stream) {
   const int w = cplx ? 2 : 1;
-  launch(k_colnorm, dim3(n), dim3(256), 0, stream, G, ldg, n, w, colmap, d);
-  launch(k_rank, dim3((n + 255) / 256), dim3(256), 0, stream, n, d, sgn, colmap, rank, lambda, st);
-  launch(k_write_v, dim3(n), dim3(256), 0, stream, G, ldg, n, w, colmap, d, rank, V, ldv);
+  launch(k_colnorm, dim3(cols), dim3(256), 0, stream, G, ldg, rows, w, colmap, d);
+  launch(k_rank, dim3((cols + 255) / 256), dim3(256), 0, stream, cols, d, sgn, colmap, rank, lambda, st);
+  launch(k_write_v, dim3(cols), dim3(256), 0, stream, G, ldg, rows, w, colmap, d, rank, V, ldv);
 }
 
 }  // namespace jj

@@ -379,7 +379,8 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
                                                     const signed char* __restrict__ sgl, double tol, int inner_max,
                                                     int mode, int soft, double* __restrict__ Wout,
                                                     int* __restrict__ rotflag, SweepStats* st0, Batch bt,
-                                                    int* __restrict__ refine, const int* __restrict__ only) {
+                                                    int* __restrict__ refine, const int* __restrict__ only,
+                                                    double* Gd, int ldgd, const int* __restrict__ cols) {
   typedef typename Scalar<CPLX>::T T;
   constexpr int NT = 64 * LPS;  // two halves of 32 slots
   constexpr int HT = 32 * LPS;  // threads of one half
@@ -397,10 +398,10 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
   T* W = lds + kMaxPivot * LDR;
   const int bslot = blockIdx.x, tid = threadIdx.x;
   if (only != nullptr && !only[bslot]) return;  // a re-solve launch: this pivot was solved
-  int p = bslot, n = n0, ldg_unused = 0;
-  double* G_unused = nullptr;
+  int p = bslot, n = n0, ldgm = ldgd;
+  double* Gm = Gd;
   SweepStats* st = st0;
-  if (!batch_resolve(bt, bslot, p, G_unused, ldg_unused, n, st)) return;
+  if (!batch_resolve(bt, bslot, p, Gm, ldgm, n, st)) return;
   // partials present for this pivot's rows (fewer than nch for short problems in a batch)
   const int nchp = min(nch, (n + rows_per_chunk - 1) / rows_per_chunk);
   if (bt.slot_prob != nullptr) {
@@ -418,6 +419,26 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
   if (refine != nullptr && tid == 0) refine[bslot] = 0;
   const signed char* sg = s_sg;  // signs of the pivot's columns, in LDS
 
+  if (mode == 3) {
+    // ---- direct (one pivot holding all n <= kMaxPivot columns of G): the
+    // non-blocked one-sided J-Jacobi on G itself (Algorithm 3.2), G's rows in
+    // place of R's; no Gram block, no Cholesky ----
+    const T* Gc = reinterpret_cast<const T*>(Gm);
+    for (int e = tid; e < kMaxPivot * kMaxPivot; e += NT) {
+      const int r = e & 63, c = e >> 6;
+      if (c < m) {
+        R[c * LDR + r] = r < n ? Gc[(size_t)cols[p * kMaxPivot + c] * ldgm + r] : zero_of(T());
+        T one = zero_of(T());
+        if constexpr (CPLX) one.x = (r == c) ? 1.0 : 0.0; else one = (r == c) ? 1.0 : 0.0;
+        W[c * LDR + r] = one;
+      }
+    }
+    if (tid == 0) {
+      s_bad = 0;
+      s_cnt = 0;
+    }
+    __syncthreads();
+  } else {
   // ---- 1. A_P = sum of the chunk partials (upper 16x16 tiles), Hermitian fill ----
   // Thread u of each 256-element tile takes element (u / 16, u % 16) of it; the
   // chunk loads of EB tiles are issued together, then summed in chunk order.
@@ -579,18 +600,21 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
     }
   }
 
+  }  // mode != 3
+
   // ---- 4. inner sweeps ----
   // half 0 (threads 0..HT-1) holds columns of R, half 1 columns of W_P in the
   // split cross pass; elsewhere half 0 works on both and half 1 waits
   const int half = tid / HT, slot = (tid % HT) / LPS, sub = tid % LPS;
   const int L = max(n1, n2);
-  const int nsweeps = mode == 0 ? inner_max : 1;
-  int total = 0, sweeps_run = 0;
+  const bool full = mode == 0 || mode == 3;  // within-block pairs too, inner sweeps up to inner_max
+  const int nsweeps = full ? inner_max : 1;
+  int total = 0, sweeps_run = 0, last_cnt = 0;
   for (int it = 0; it < nsweeps; it++) {
     int cnt = 0;
     sweeps_run++;
     // (a) within-block pairs, circle round-robin on each block, data in LDS
-    if (mode == 0) {
+    if (full) {
       const int blk = slot >> 4, hs = slot & 15;  // slots 0-15: block 1, 16-31: block 2
       const int nb = blk == 0 ? n1 : n2, base = blk == 0 ? 0 : n1;
       const int nbp = nb + (nb & 1);
@@ -621,15 +645,19 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
           double cs, sn, pr, pi;
           int rc = pair_rotation(arr, ass, are, aim, CPLX, sigma, tol, &cs, &sn, &pr, &pi);
           if (rc > 0) {
-            T* Wr = W + (base + r) * LDR;
-            T* Ws = W + (base + s) * LDR;
             for (int i = sub; i < m; i += LPS) {
               T f = phase_mul(pr, pi, Rr[i]), g = Rs[i];
               Rr[i] = lin2(cs, f, -sigma * sn, g);
               Rs[i] = lin2(sn, f, cs, g);
-              T u = phase_mul(pr, pi, Wr[i]), w = Ws[i];
-              Wr[i] = lin2(cs, u, -sigma * sn, w);
-              Ws[i] = lin2(sn, u, cs, w);
+            }
+            if (mode != 3) {  // the direct mode keeps no W_P
+              T* Wr = W + (base + r) * LDR;
+              T* Ws = W + (base + s) * LDR;
+              for (int i = sub; i < m; i += LPS) {
+                T u = phase_mul(pr, pi, Wr[i]), w = Ws[i];
+                Wr[i] = lin2(cs, u, -sigma * sn, w);
+                Ws[i] = lin2(sn, u, cs, w);
+              }
             }
             cnt += (sub == 0);
           } else if (rc < 0 && sub == 0) {
@@ -890,6 +918,7 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
     __syncthreads();
     if (tid == 0) s_cnt = 0;
     total += c_all;
+    last_cnt = c_all;
     if (c_all == 0) break;
     __syncthreads();
   }
@@ -905,6 +934,26 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
     // handed on to the FP64 re-solve of this step, which writes W_P, the flag
     // and the counters of this pivot
     if (tid == 0) rotflag[bslot] = 0;
+    return;
+  }
+
+  if (mode == 3) {
+    // G~ = G W: the rotated columns go back to G; converged iff the last inner
+    // sweep applied no rotation (counted in pivots_rotated otherwise)
+    T* Gc = reinterpret_cast<T*>(Gm);
+    if (!s_bad)
+      for (int e = tid; e < kMaxPivot * kMaxPivot; e += NT) {
+        const int r = e & 63, c = e >> 6;
+        if (c < m && r < n) Gc[(size_t)cols[p * kMaxPivot + c] * ldgm + r] = R[c * LDR + r];
+      }
+    if (tid == 0) {
+      rotflag[bslot] = 0;
+      if (last_cnt > 0) atomicAdd(&st->pivots_rotated, 1);
+      atomicAdd(&st->rotations, (unsigned long long)total);
+      atomicAdd(&st->inner_sweeps, (unsigned long long)sweeps_run);
+      atomicAdd(&st->pivot_cols, (unsigned long long)m);
+      atomicAdd(&st->pivot_cols3, (unsigned long long)m * m * m);
+    }
     return;
   }
 
@@ -931,25 +980,29 @@ constexpr int kPivotLPS = 8;
 
 void launch_pivot_f64(const double* part, int nch, int n, int rows_per_chunk, const PivotList& pl, double tol,
                       int inner_max, int inner_mode, int soft, double* W, int* rotflag, SweepStats* st,
-                      hipStream_t stream, const Batch& b, int* refine, const int* only) {
+                      hipStream_t stream, const Batch& b, int* refine, const int* only, double* G, int ldg) {
   // batched launches: two workgroups per CU, lane-read Cholesky (register budget)
   if (b.slot_prob != nullptr)
     launch((k_pivot<false, kPivotLPS, true, 0>), dim3(pl.count), dim3(64 * kPivotLPS), 0, stream, part, nch, n,
-           rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st, b, refine, only);
+           rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st, b, refine, only,
+           G, ldg, pl.cols);
   // full diagonalisation (mode 0, several inner sweeps): the lane-read Cholesky
-  else if (inner_mode == 0 && inner_max > 1)
+  else if ((inner_mode == 0 && inner_max > 1) || inner_mode == 3)
     launch((k_pivot<false, kPivotLPS, false, 0>), dim3(pl.count), dim3(64 * kPivotLPS), 0, stream, part, nch, n,
-           rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st, b, refine, only);
+           rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st, b, refine, only,
+           G, ldg, pl.cols);
   else
     launch((k_pivot<false, kPivotLPS, false, 1>), dim3(pl.count), dim3(64 * kPivotLPS), 0, stream, part, nch, n,
-           rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st, b, refine, only);
+           rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st, b, refine, only,
+           G, ldg, pl.cols);
 }
 
 void launch_pivot_c128(const double* part, int nch, int n, int rows_per_chunk, const PivotList& pl, double tol,
                        int inner_max, int inner_mode, int soft, double* W, int* rotflag, SweepStats* st,
-                       hipStream_t stream, const Batch& b, int* refine, const int* only) {
+                       hipStream_t stream, const Batch& b, int* refine, const int* only, double* G, int ldg) {
   launch((k_pivot<true, kPivotLPS, false, 2>), dim3(pl.count), dim3(64 * kPivotLPS), 0, stream, part, nch, n,
-                     rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st, b, refine, only);
+                     rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st, b, refine, only,
+           G, ldg, pl.cols);
 }
 
 }  // namespace jj

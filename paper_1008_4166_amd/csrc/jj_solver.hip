@@ -266,6 +266,20 @@ static void build_pairs_tables(Plan& P, const std::vector<int>& pairs, int nstep
   const int h = P.nbl / 2;
   P.nsteps = nsteps;
   P.npairs_max = h;
+  int bmax = 0;
+  for (int l = 0; l < P.nbl; l++) bmax = std::max(bmax, P.off[l + 1] - P.off[l]);
+  if (2 * bmax > kMaxPivot) {
+    // three-level pivots: only the pairs' blocks are tabulated here (the
+    // sub-pivot tables are built by build_three_tables)
+    P.count = counts;
+    P.pblocks.assign((size_t)nsteps * h * 2, -1);
+    for (int t = 0; t < nsteps; t++)
+      for (int k = 0; k < counts[t]; k++) {
+        P.pblocks[((size_t)t * h + k) * 2] = pairs[(t * h + k) * 2];
+        P.pblocks[((size_t)t * h + k) * 2 + 1] = pairs[(t * h + k) * 2 + 1];
+      }
+    return;
+  }
   P.cols.assign((size_t)nsteps * h * kMaxPivot, -1);
   P.sgp.assign((size_t)nsteps * h * kMaxPivot, 0);
   P.m.assign((size_t)nsteps * h, 0);
@@ -339,6 +353,74 @@ static void build_diag_tables(const Plan& P, std::vector<int>& cols, std::vector
   }
 }
 
+// Tables of the three-level pivots (Section 5, Algorithm 5.1) for pairs of
+// blocks I, J of up to 64 columns, halves I = I1 I2, J = J1 J2 (the first half
+// takes the odd column):
+//   six 64-column sub-pivots per pair whose Gram blocks cover A_P's upper
+//   triangle: I, J, I1 J1, I1 J2, I2 J1, I2 J2 (physical columns of G);
+//   inner pivots, two per pair in each of three inner steps: step 0 (the first
+//   step of a sweep only) (I1 I2), (J1 J2), a full pass; step 1 (I1 J1),
+//   (I2 J2) and step 2 (I1 J2), (I2 J1), passes over their off-diagonal blocks;
+//   each with its columns in the pair's slot of the R workspace (pair k at
+//   columns 128 k ...: I first, then J) and in G.
+struct ThreeTables {
+  std::vector<int> vcols, vm, n1, n2, icolR, icolG, im, inf;
+  std::vector<signed char> isg;
+};
+static void build_three_tables(const Plan& P, ThreeTables& T) {
+  const int h = std::max(P.npairs_max, 1);
+  const size_t NP = (size_t)P.nsteps * h;
+  T.vcols.assign(NP * 6 * kMaxPivot, -1);
+  T.vm.assign(NP * 6, 0);
+  T.n1.assign(NP, 0);
+  T.n2.assign(NP, 0);
+  T.icolR.assign(NP * 3 * 2 * kMaxPivot, -1);
+  T.icolG.assign(NP * 3 * 2 * kMaxPivot, -1);
+  T.isg.assign(NP * 3 * 2 * kMaxPivot, 0);
+  T.im.assign(NP * 3 * 2, 0);
+  T.inf.assign(NP * 3 * 2, 0);
+  for (int t = 0; t < P.nsteps; t++)
+    for (int k = 0; k < P.count[t]; k++) {
+      const size_t pr = (size_t)t * h + k;
+      const int bi = P.pblocks[pr * 2], bj = P.pblocks[pr * 2 + 1];
+      const int nI = P.off[bi + 1] - P.off[bi], nJ = P.off[bj + 1] - P.off[bj];
+      const int a1 = (nI + 1) / 2, b1 = (nJ + 1) / 2;
+      T.n1[pr] = nI;
+      T.n2[pr] = nJ;
+      // local column l (0 .. nI + nJ - 1): physical column and sign
+      auto phys = [&](int l) { return P.colmap[l < nI ? P.off[bi] + l : P.off[bj] + l - nI]; };
+      auto sign = [&](int l) { return P.sgn[l < nI ? P.off[bi] + l : P.off[bj] + l - nI]; };
+      // local ranges [lo, hi) of I1, I2, J1, J2
+      const int rg[4][2] = {{0, a1}, {a1, nI}, {nI, nI + b1}, {nI + b1, nI + nJ}};
+      auto fill = [&](int* cols, int* mm, int* nf, signed char* sg, int colbase, bool phys_cols, int x, int y) {
+        int c = 0;
+        for (int l = rg[x][0]; l < rg[x][1]; l++, c++) {
+          cols[c] = phys_cols ? phys(l) : colbase + l;
+          if (sg) sg[c] = sign(l);
+        }
+        if (nf) *nf = c;
+        for (int l = rg[y][0]; l < rg[y][1]; l++, c++) {
+          cols[c] = phys_cols ? phys(l) : colbase + l;
+          if (sg) sg[c] = sign(l);
+        }
+        *mm = c;
+      };
+      const int sub[6][2] = {{0, 1}, {2, 3}, {0, 2}, {0, 3}, {1, 2}, {1, 3}};
+      for (int v = 0; v < 6; v++)
+        fill(&T.vcols[(pr * 6 + v) * kMaxPivot], &T.vm[pr * 6 + v], nullptr, nullptr, 0, true, sub[v][0],
+             sub[v][1]);
+      const int inner[3][2][2] = {{{0, 1}, {2, 3}}, {{0, 2}, {1, 3}}, {{0, 3}, {1, 2}}};
+      for (int s = 0; s < 3; s++)
+        for (int q = 0; q < 2; q++) {
+          const size_t e = (((size_t)t * 3 + s) * h + k) * 2 + q;
+          fill(&T.icolR[e * kMaxPivot], &T.im[e], &T.inf[e], &T.isg[e * kMaxPivot], k * 2 * kMaxPivot, false,
+               inner[s][q][0], inner[s][q][1]);
+          int mm = 0;
+          fill(&T.icolG[e * kMaxPivot], &mm, nullptr, nullptr, 0, true, inner[s][q][0], inner[s][q][1]);
+        }
+    }
+}
+
 // The library's own non-blocking stream on the current device: solves run on
 // it (a HIP graph cannot be captured on the legacy default stream), ordered
 // after the caller's stream on entry; on scope exit the caller's stream is
@@ -378,11 +460,15 @@ static int size_bucket(int n) {
   while ((64 << b) < n && b < 12) b++;
   return b;  // 0: n <= 64, 1: <= 128, 2: <= 256, ...
 }
-static int tune_block_width(int dtype, void* G, const signed char* J, int n, int ldg, hipStream_t stream);
-static int tuned_block_width(int dtype, void* G, const signed char* J, int n, int ldg, hipStream_t stream) {
-  const auto key = std::make_pair(dtype, size_bucket(n));
+static int tune_block_width(int dtype, void* G, const signed char* J, int n, int ldg, hipStream_t stream,
+                            bool wide);
+// wide: 64 (three-level pivots) is a candidate too (single solves; the batched
+// form takes at most 32); cached separately
+static int tuned_block_width(int dtype, void* G, const signed char* J, int n, int ldg, hipStream_t stream,
+                             bool wide = false) {
+  const auto key = std::make_pair(dtype + (wide ? 2 : 0), size_bucket(n));
   auto it = g_tuned_bw.find(key);
-  if (it == g_tuned_bw.end()) it = g_tuned_bw.emplace(key, tune_block_width(dtype, G, J, n, ldg, stream)).first;
+  if (it == g_tuned_bw.end()) it = g_tuned_bw.emplace(key, tune_block_width(dtype, G, J, n, ldg, stream, wide)).first;
   return it->second;
 }
 
@@ -390,10 +476,13 @@ static int tuned_block_width(int dtype, void* G, const signed char* J, int n, in
 // the caller's stream (no library stream, events, graphs or block-width tuning:
 // each of those allocates), and a solve whose workspace exceeds the scratch
 // throws ScratchTooSmall before any device work.
+// m_rows: rows of G (0: square, m = n); a rectangular G (m > n, full column
+// rank) is the factor of a singular H of rank n (Section 2.2).
 static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, double* lambda, void* Vv,
                      int ldv, double tol, int max_sweeps, const jj_opts& o, jj_info* info, bool graphs_ok = true,
-                     bool noalloc = false) {
+                     bool noalloc = false, int m_rows = 0) {
   auto t0 = std::chrono::steady_clock::now();
+  const int m = m_rows > 0 ? m_rows : n;
   const int cplx = dtype == JJ_C128;
   double* G = (double*)Gv;
   double* V = (double*)Vv;
@@ -402,20 +491,38 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
   StreamJoin join(noalloc ? stream : (hipStream_t)o.stream, stream);
   // block width: the caller's, else tuned for large problems (first use of a
   // size bucket), else 32
-  int nt = o.block_width > 0 ? std::min(o.block_width, kMaxBlock) : 32;
-  if (o.block_width <= 0 && graphs_ok && n >= 1024) nt = tuned_block_width(dtype, Gv, J, n, ldg, stream);
+  // (widths above 32 make three-level pivots: plain FP64, block-oriented, no
+  // diagonal pass, one step at a time; other option sets take 32)
+  const bool three_ok = o.precision == 0 && o.diag_pass == 0 && o.inner_mode == 0 && o.step_groups <= 1;
+  int nt = o.block_width > 0 ? std::min(o.block_width, three_ok ? 2 * kMaxBlock : kMaxBlock) : 32;
+  if (o.block_width <= 0 && graphs_ok && m == n && n >= 1024)
+    nt = tuned_block_width(dtype, Gv, J, n, ldg, stream, three_ok);
   const int inner_max = o.inner_max_sweeps > 0 ? o.inner_max_sweeps : 12;
-  if (tol <= 0.0) tol = (double)n * std::ldexp(1.0, -53);
+  if (tol <= 0.0) tol = (double)m * std::ldexp(1.0, -53);
   if (max_sweeps <= 0) max_sweeps = 100;
 
   Plan P = make_plan(n, J, nt, o.strategy);
   const int h = std::max(P.npairs_max, 1);
+  int bmax = 0;
+  for (int l = 0; l < P.nbl; l++) bmax = std::max(bmax, P.off[l + 1] - P.off[l]);
+  const bool three = P.nsteps > 0 && 2 * bmax > kMaxPivot;
+  ThreeTables T3;
+  int nch3 = 1, rows_g3 = 64, rows_u3 = 64;
+  if (three) {
+    build_three_tables(P, T3);
+    // the six sub-pivot Gram blocks of a step: about 1024 workgroups
+    nch3 = std::max(1, std::min(std::min((1024 + 6 * h - 1) / (6 * h), (m + 63) / 64), kMaxChunks));
+    rows_g3 = ((m + nch3 - 1) / nch3 + 63) / 64 * 64;
+    nch3 = (m + rows_g3 - 1) / rows_g3;
+    rows_u3 = ((long long)2 * h * ((m + 255) / 256) < 512) ? 64 : 256;
+  }
+  const size_t NP3 = three ? (size_t)P.nsteps * h : 0;
   // chunking of the row dimension for the Gram and update kernels
-  int nch = std::max(1, std::min(std::min((1024 + h - 1) / h, (n + 63) / 64), kMaxChunks));
-  int rows_g = ((n + nch - 1) / nch + 63) / 64 * 64;
-  nch = (n + rows_g - 1) / rows_g;
+  int nch = std::max(1, std::min(std::min((1024 + h - 1) / h, (m + 63) / 64), kMaxChunks));
+  int rows_g = ((m + nch - 1) / nch + 63) / 64 * 64;
+  nch = (m + rows_g - 1) / rows_g;
   int rows_u = 256;
-  if ((long long)h * ((n + 255) / 256) < 512) rows_u = 64;
+  if ((long long)h * ((m + 255) / 256) < 512) rows_u = 64;
 
   std::vector<int> dcols, dm, dnf;
   std::vector<signed char> dsg;
@@ -445,6 +552,22 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
     c.take<signed char>(n);
     c.take<double>(n);
     c.take<int>(n);
+    if (three) {
+      c.take<int>(NP3 * 6 * kMaxPivot);
+      c.take<int>(NP3 * 6);
+      c.take<int>(NP3);
+      c.take<int>(NP3);
+      c.take<int>(NP3 * 6 * kMaxPivot);
+      c.take<int>(NP3 * 6 * kMaxPivot);
+      c.take<signed char>(NP3 * 6 * kMaxPivot);
+      c.take<int>(NP3 * 6);
+      c.take<int>(NP3 * 6);
+      c.take<double>((size_t)6 * h * nch3 * kMaxPivot * kMaxPivot * (cplx ? 2 : 1));
+      c.take<double>((size_t)h * kMaxPivot3 * kMaxPivot3 * (cplx ? 2 : 1));
+      c.take<double>((size_t)2 * h * kMaxPivot * kMaxPivot * (cplx ? 2 : 1));
+      c.take<double>((size_t)2 * h * kMaxPivot * kMaxPivot * (cplx ? 2 : 1));
+      c.take<int>((size_t)2 * h);
+    }
     need = c.off + 256;
   }
   if (noalloc && need > kScratchBytes) throw ScratchTooSmall{need};
@@ -466,8 +589,41 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
   signed char* d_sgn = c.take<signed char>(n);
   double* d_d = c.take<double>(n);
   int* d_rank = c.take<int>(n);
+  // three-level pivots: sub-pivot and inner tables, Gram partials, R slots
+  int *d_vcols = nullptr, *d_vm = nullptr, *d_n1 = nullptr, *d_n2 = nullptr, *d_icolR = nullptr,
+      *d_icolG = nullptr, *d_im = nullptr, *d_inf = nullptr, *d_irot = nullptr;
+  signed char* d_isg = nullptr;
+  double *d_vpart = nullptr, *d_RW = nullptr, *d_ipart = nullptr, *d_iW = nullptr;
+  if (three) {
+    d_vcols = c.take<int>(NP3 * 6 * kMaxPivot);
+    d_vm = c.take<int>(NP3 * 6);
+    d_n1 = c.take<int>(NP3);
+    d_n2 = c.take<int>(NP3);
+    d_icolR = c.take<int>(NP3 * 6 * kMaxPivot);
+    d_icolG = c.take<int>(NP3 * 6 * kMaxPivot);
+    d_isg = c.take<signed char>(NP3 * 6 * kMaxPivot);
+    d_im = c.take<int>(NP3 * 6);
+    d_inf = c.take<int>(NP3 * 6);
+    d_vpart = c.take<double>((size_t)6 * h * nch3 * kMaxPivot * kMaxPivot * (cplx ? 2 : 1));
+    d_RW = c.take<double>((size_t)h * kMaxPivot3 * kMaxPivot3 * (cplx ? 2 : 1));
+    d_ipart = c.take<double>((size_t)2 * h * kMaxPivot * kMaxPivot * (cplx ? 2 : 1));
+    d_iW = c.take<double>((size_t)2 * h * kMaxPivot * kMaxPivot * (cplx ? 2 : 1));
+    d_irot = c.take<int>((size_t)2 * h);
+    auto up = [&](void* dst, const void* src, size_t bytes) {
+      ck(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream), "H2D");
+    };
+    up(d_vcols, T3.vcols.data(), T3.vcols.size() * sizeof(int));
+    up(d_vm, T3.vm.data(), T3.vm.size() * sizeof(int));
+    up(d_n1, T3.n1.data(), T3.n1.size() * sizeof(int));
+    up(d_n2, T3.n2.data(), T3.n2.size() * sizeof(int));
+    up(d_icolR, T3.icolR.data(), T3.icolR.size() * sizeof(int));
+    up(d_icolG, T3.icolG.data(), T3.icolG.size() * sizeof(int));
+    up(d_isg, T3.isg.data(), T3.isg.size());
+    up(d_im, T3.im.data(), T3.im.size() * sizeof(int));
+    up(d_inf, T3.inf.data(), T3.inf.size() * sizeof(int));
+  }
 
-  if (P.nsteps > 0) {
+  if (P.nsteps > 0 && !three) {
     ck(hipMemcpyAsync(d_cols, P.cols.data(), P.cols.size() * sizeof(int), hipMemcpyHostToDevice, stream), "H2D");
     ck(hipMemcpyAsync(d_sg, P.sgp.data(), P.sgp.size(), hipMemcpyHostToDevice, stream), "H2D");
     ck(hipMemcpyAsync(d_m, P.m.data(), P.m.size() * sizeof(int), hipMemcpyHostToDevice, stream), "H2D");
@@ -489,7 +645,7 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
   SweepStats hst;
   size_t e0 = prof.mark();
   launch_reset_stats(d_st, stream);
-  launch_check_finite(G, ldg, n, cplx, d_st, stream);
+  launch_check_finite(G, ldg, m, n, cplx, d_st, stream);
   prof.done(JJ_K_OTHER, e0, 0);
   ck(hipGetLastError(), "launch");
   ck(hipMemcpyAsync(&hst, d_st, sizeof(hst), hipMemcpyDeviceToHost, stream), "D2H");
@@ -533,21 +689,21 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
                         int mode, int imax, const std::function<void()>& after_first = nullptr) {
     size_t k0 = prof.arm();
     if (use_mix)
-      gram32(G, ldg, n, pl, nch, rows_g, part, stream, Batch());
+      gram32(G, ldg, m, pl, nch, rows_g, part, stream, Batch());
     else
-      gram64(G, ldg, n, pl, nch, rows_g, part, stream, Batch(), nullptr);
+      gram64(G, ldg, m, pl, nch, rows_g, part, stream, Batch(), nullptr);
     prof.done_kernel(JJ_K_GRAM, k0, pl.count);
     if (after_first) after_first();
     k0 = prof.arm();
-    pivot(part, nch, n, rows_g, pl, use_mix ? tol_mix : tol, imax, mode, use_mix, W, rot, d_st, stream, Batch(),
-          use_mix ? refine : nullptr, nullptr);
+    pivot(part, nch, m, rows_g, pl, use_mix ? tol_mix : tol, imax, mode, use_mix, W, rot, d_st, stream, Batch(),
+          use_mix ? refine : nullptr, nullptr, G, ldg);
     prof.done_kernel(JJ_K_PIVOT, k0, pl.count);
     if (use_mix) {
       k0 = prof.arm();
-      gram64(G, ldg, n, pl, nch, rows_g, part, stream, Batch(), refine);
+      gram64(G, ldg, m, pl, nch, rows_g, part, stream, Batch(), refine);
       prof.done_kernel(JJ_K_GRAM, k0, 0);
       k0 = prof.arm();
-      pivot(part, nch, n, rows_g, pl, tol, imax, mode, 0, W, rot, d_st, stream, Batch(), nullptr, refine);
+      pivot(part, nch, m, rows_g, pl, tol, imax, mode, 0, W, rot, d_st, stream, Batch(), nullptr, refine, G, ldg);
       prof.done_kernel(JJ_K_PIVOT, k0, 0);
     }
   };
@@ -559,10 +715,45 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
       PivotList dl{d_dcols, d_dsg, d_dm, d_dnf, P.nbl};
       gram_pivot(use_mix, dl, d_part, d_W, d_rot, d_refine, 0, inner_max);
       k0 = prof.arm();
-      update(G, ldg, n, dl, d_W, d_rot, rows_u, stream, Batch(), 0);
+      update(G, ldg, m, dl, d_W, d_rot, rows_u, stream, Batch(), 0);
       prof.done_kernel(JJ_K_UPDATE, k0, 0);
     }
-    for (int t = 0; t < P.nsteps; t++) {
+    for (int t = 0; t < P.nsteps && three; t++) {
+      // three-level step (Section 5.3 with step 3 by the blocked method,
+      // Algorithm 5.1): Gram blocks of the six sub-pivots of every pair, A_P =
+      // R^* R, then the inner steps on R, each inner transformation applied to
+      // R and to the pair's columns of G
+      const int cnt = P.count[t];
+      if (cnt == 0) continue;
+      const size_t pr0 = (size_t)t * h;
+      PivotList vl{d_vcols + pr0 * 6 * kMaxPivot, d_isg, d_vm + pr0 * 6, d_vm + pr0 * 6, 6 * cnt};
+      k0 = prof.arm();
+      gram64(G, ldg, m, vl, nch3, rows_g3, d_vpart, stream, Batch(), nullptr);
+      prof.done_kernel(JJ_K_GRAM, k0, vl.count);
+      k0 = prof.arm();
+      launch_chol128(cplx != 0, d_vpart, nch3, m, rows_g3, d_n1 + pr0, d_n2 + pr0, cnt, d_RW, kMaxPivot3, t == 0,
+                     d_st, stream);
+      prof.done_kernel(JJ_K_PIVOT, k0, 0);
+      for (int sidx = t == 0 ? 0 : 1; sidx < 3; sidx++) {
+        const size_t base = ((size_t)t * 3 + sidx) * h * 2;
+        PivotList ilR{d_icolR + base * kMaxPivot, d_isg + base * kMaxPivot, d_im + base, d_inf + base, 2 * cnt};
+        PivotList ilG{d_icolG + base * kMaxPivot, d_isg + base * kMaxPivot, d_im + base, d_inf + base, 2 * cnt};
+        k0 = prof.arm();
+        gram64(d_RW, kMaxPivot3, kMaxPivot3, ilR, 1, kMaxPivot3, d_ipart, stream, Batch(), nullptr);
+        prof.done_kernel(JJ_K_GRAM, k0, 0);
+        k0 = prof.arm();
+        pivot(d_ipart, 1, kMaxPivot3, kMaxPivot3, ilR, tol, 1, sidx == 0 ? 0 : 1, 0, d_iW, d_irot, d_st, stream,
+              Batch(), nullptr, nullptr, d_RW, kMaxPivot3);
+        prof.done_kernel(JJ_K_PIVOT, k0, ilR.count);
+        k0 = prof.arm();
+        update(d_RW, kMaxPivot3, kMaxPivot3, ilR, d_iW, d_irot, 64, stream, Batch(), 0);
+        prof.done_kernel(JJ_K_UPDATE, k0, 0);
+        k0 = prof.arm();
+        update(G, ldg, m, ilG, d_iW, d_irot, rows_u3, stream, Batch(), 0);
+        prof.done_kernel(JJ_K_UPDATE, k0, 0);
+      }
+    }
+    for (int t = 0; t < P.nsteps && !three; t++) {
       PivotList pl{d_cols + (size_t)t * h * kMaxPivot, d_sg + (size_t)t * h * kMaxPivot, d_m + (size_t)t * h,
                    d_nf + (size_t)t * h, P.count[t]};
       if (pl.count == 0) continue;
@@ -576,7 +767,7 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
       const int imax = block_oriented ? 1 : inner_max;
       gram_pivot(use_mix, pl, d_part, d_W, d_rot, d_refine, mode, imax);
       k0 = prof.arm();
-      update(G, ldg, n, pl, d_W, d_rot, rows_u, stream, Batch(), 0);
+      update(G, ldg, m, pl, d_W, d_rot, rows_u, stream, Batch(), 0);
       prof.done_kernel(JJ_K_UPDATE, k0, 0);
     }
   };
@@ -590,7 +781,7 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
   // kernels), and every task still reads exactly the data the sequential order
   // gives it, so the results are those of the eager sweep.
   const int wsz = cplx ? 2 : 1;
-  const int ngrp = (o.step_groups <= 1 || h < 8) ? 1 : std::min(o.step_groups, std::min(h / 4, kMaxStepGroups));
+  const int ngrp = (o.step_groups <= 1 || h < 8 || three) ? 1 : std::min(o.step_groups, std::min(h / 4, kMaxStepGroups));
   struct Task {
     hipGraphNode_t first, last;
     std::vector<int> deps;
@@ -620,7 +811,7 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
       double* W = d_W + s0 * kMaxPivot * kMaxPivot * wsz;
       int* rot = d_rot + s0;
       gram_pivot(use_mix, pl, part, W, rot, d_refine + s0, mode, imax, [&]() { tk.first = last_node(); });
-      update(G, ldg, n, pl, W, rot, rows_u, stream, Batch(), 0);
+      update(G, ldg, m, pl, W, rot, rows_u, stream, Batch(), 0);
       tk.last = last_node();
       for (int b : blocks) owner[b] = (int)tasks.size();
       tasks.push_back(std::move(tk));
@@ -669,7 +860,34 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
     }
   };
   SweepGraphs graphs;
-  while (P.nbl >= 2 && sweep < max_sweeps) {
+  // At most kMaxPivot columns and rows (two blocks: a single pivot holding the
+  // whole matrix): the non-blocked process on G itself in one launch
+  // (Algorithm 3.2, inner sweeps until one applies no rotation, capped by
+  // max_sweeps): no Gram block, no Cholesky, no update.  sweeps counts its
+  // sweeps.
+  const bool direct = P.nbl == 2 && P.nsteps == 1 && m == n && n <= kMaxPivot && !mixed && o.diag_pass == 0;
+  if (direct) {
+    PivotList pl{d_cols, d_sg, d_m, d_nf, P.count[0]};
+    size_t k0 = prof.arm();
+    pivot(d_part, nch, m, rows_g, pl, tol, max_sweeps, 3, 0, d_W, d_rot, d_st, stream, Batch(), nullptr, nullptr, G,
+          ldg);
+    prof.done_kernel(JJ_K_PIVOT, k0, pl.count);
+    ck(hipGetLastError(), "launch");
+    ck(hipMemcpyAsync(&hst, d_st, sizeof(hst), hipMemcpyDeviceToHost, stream), "D2H");
+    ck(hipStreamSynchronize(stream), "sync");
+    prof.flush();
+    sweep = (int)hst.inner_sweeps;
+    piv_rot = hst.rotations > 0 ? 1 : 0;
+    prof.acc.rotations += (long long)hst.rotations;
+    prof.acc.inner_sweeps += (long long)hst.inner_sweeps;
+    prof.acc.pivot_cols += (long long)hst.pivot_cols;
+    prof.acc.pivot_cols3 += (long long)hst.pivot_cols3;
+    if (hst.breakdown)
+      breakdown = true;
+    else if (hst.pivots_rotated == 0)
+      status = JJ_OK;
+  }
+  while (!direct && P.nbl >= 2 && sweep < max_sweeps) {
     sweep++;
     const bool use_mix = mixed;
     const bool diag = o.diag_pass == 2 || (o.diag_pass == 1 && sweep == 1);
@@ -744,7 +962,7 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
   launch_reset_stats(d_st, stream);
   prof.done(JJ_K_OTHER, e0, 0);
   e0 = prof.mark();
-  launch_finalize(G, ldg, n, cplx, d_colmap, d_sgn, d_d, d_rank, lambda, V, ldv, d_st, stream);
+  launch_finalize(G, ldg, m, n, cplx, d_colmap, d_sgn, d_d, d_rank, lambda, V, ldv, d_st, stream);
   prof.done(JJ_K_FINAL, e0, n);
   ck(hipGetLastError(), "launch");
   ck(hipMemcpyAsync(&hst, d_st, sizeof(hst), hipMemcpyDeviceToHost, stream), "D2H");
@@ -794,7 +1012,8 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
 // small problem and picked the slower width.
 
 
-static int tune_block_width(int dtype, void* G, const signed char* J, int n, int ldg, hipStream_t stream) {
+static int tune_block_width(int dtype, void* G, const signed char* J, int n, int ldg, hipStream_t stream,
+                            bool wide) {
   const int w = dtype == JJ_C128 ? 2 : 1;
   if (n <= 64) return 32;  // one pivot holds the whole problem for either width
   const size_t gsz = (size_t)n * n * w * sizeof(double);
@@ -805,9 +1024,15 @@ static int tune_block_width(int dtype, void* G, const signed char* J, int n, int
   hipEvent_t e0, e1;
   ck(hipEventCreate(&e0), "event");
   ck(hipEventCreate(&e1), "event");
+  // Up to n = 2048 each candidate runs a whole solve (time to solution: the
+  // widths need different sweep counts); above, two sweeps (a solve there
+  // takes from 0.2 s to seconds, and the measured sweep counts of the widths
+  // differ by a few percent).
+  const bool whole = n <= 2048;
   int best = 32;
   float best_ms = 1e30f;
-  const int cand[2] = {32, 16};
+  std::vector<int> cand = {32, 16};
+  if (wide) cand.push_back(64);
   for (int c : cand) {  // untimed: workspace growth and first launches
     ck(hipMemcpy2DAsync(Gc, (size_t)n * w * sizeof(double), G, (size_t)ldg * w * sizeof(double),
                         (size_t)n * w * sizeof(double), n, hipMemcpyDeviceToDevice, stream),
@@ -827,7 +1052,7 @@ static int tune_block_width(int dtype, void* G, const signed char* J, int n, int
     o.stream = stream;
     o.block_width = c;
     ck(hipEventRecord(e0, stream), "event");
-    solve_one(dtype, Gc, J, n, n, lam, V, n, 0.0, 2, o, nullptr, false);
+    solve_one(dtype, Gc, J, n, n, lam, V, n, 0.0, whole ? 0 : 2, o, nullptr, whole);
     ck(hipEventRecord(e1, stream), "event");
     ck(hipEventSynchronize(e1), "event");
     float ms = 0.f;
@@ -1115,7 +1340,7 @@ static int solve_batch(int count, const int* dtype, void* const* G, const signed
       if (grp[g].slots == 0) continue;
       PivotList pl{dg[g].cols, dg[g].sg, dg[g].m, dg[g].nfirst, grp[g].slots};
       (g ? launch_pivot_c128 : launch_pivot_f64)(dg[g].part, 1, 0, rows_g[g], pl, btol, imax, pmode, 0, dg[g].W,
-                                                 dg[g].rot, nullptr, s, bt[g], nullptr, nullptr);
+                                                 dg[g].rot, nullptr, s, bt[g], nullptr, nullptr, nullptr, 0);
     }
     for (int g = 0; g < 2; g++) {
       if (grp[g].slots == 0) continue;
@@ -1215,6 +1440,56 @@ static int solve_batch(int count, const int* dtype, void* const* G, const signed
   return worst;
 }
 
+// Front end (Section 2.2, eq. 2.5): H (device, n x n, lower triangle read) ->
+// G (device, n x n, ld ldg: the first r columns, the others zeroed), J and r on
+// the host.  A step is a pivot-choice launch and an update launch; the n + 1
+// steps are enqueued without host decisions (steps past the end return at
+// once).  Returns 0, or JJ_NONFINITE.
+static int bp_factor_dev(int dtype, const void* H, int n, int ldh, double* G, int ldg, signed char* J, int* rank,
+                         double tol, hipStream_t stream) {
+  const int w = dtype == JJ_C128 ? 2 : 1;
+  if (tol <= 0.0) tol = (double)n * std::ldexp(1.0, -53);
+  size_t need = 0;
+  {
+    Carver c{nullptr};
+    c.take<double>((size_t)n * n * w);
+    c.take<double>((size_t)n * 2 * w);
+    c.take<BPPartial>(kBpGroups);
+    c.take<BPState>(1);
+    c.take<int>(n);
+    c.take<int>(n);
+    c.take<double>((size_t)2 * n);
+    c.take<signed char>(n);
+    need = c.off + 256;
+  }
+  Carver c{arena_get(need)};
+  double* A = c.take<double>((size_t)n * n * w);
+  double* pcol = c.take<double>((size_t)n * 2 * w);
+  BPPartial* part = c.take<BPPartial>(kBpGroups);
+  BPState* st = c.take<BPState>(1);
+  int* perm = c.take<int>(n);
+  int* piv = c.take<int>(n);
+  double* dblk = c.take<double>((size_t)2 * n);
+  signed char* Jd = c.take<signed char>(n);
+  ck(hipMemcpy2DAsync(A, (size_t)n * w * sizeof(double), H, (size_t)ldh * w * sizeof(double),
+                      (size_t)n * w * sizeof(double), n, hipMemcpyDeviceToDevice, stream),
+     "copy H");
+  launch_bp_init(st, perm, n, stream);
+  launch_bp_update(A, n, w == 2, pcol, st, part, stream);  // the first search (no update yet)
+  for (int step = 0; step <= n; step++) {
+    launch_bp_select(A, n, w == 2, tol, pcol, st, part, perm, piv, dblk, stream);
+    launch_bp_update(A, n, w == 2, pcol, st, part, stream);
+  }
+  launch_bp_build_g(A, n, w == 2, st, perm, piv, dblk, G, ldg, Jd, stream);
+  ck(hipGetLastError(), "launch");
+  BPState hst;
+  ck(hipMemcpyAsync(&hst, st, sizeof(hst), hipMemcpyDeviceToHost, stream), "D2H");
+  ck(hipMemcpyAsync(J, Jd, n, hipMemcpyDeviceToHost, stream), "D2H");
+  ck(hipStreamSynchronize(stream), "sync");
+  *rank = hst.nonfinite ? 0 : hst.rank;
+  return hst.nonfinite ? JJ_NONFINITE : JJ_OK;
+}
+
 static int check_args(int dtype, const void* G, const signed char* J, int n, int ldg, const double* lambda,
                       const void* V, int ldv) {
   if (dtype != JJ_F64 && dtype != JJ_C128) return -1;
@@ -1288,6 +1563,122 @@ int jjacobi_solve_noalloc(int dtype, void* G, const signed char* J, int n, int l
     g_last_error = msg;
     if (info) info->status = JJ_SCRATCH_TOO_SMALL;
     return JJ_SCRATCH_TOO_SMALL;
+  } catch (const HipFail&) {
+    if (info) info->status = JJ_HIP_ERROR;
+    return JJ_HIP_ERROR;
+  }
+}
+
+int jjacobi_solve_rect(int dtype, void* G, const signed char* J, int m, int n, int ldg, double* lambda, void* V,
+                       int ldv, double tol, int max_sweeps, const jj_opts* opts, jj_info* info) {
+  int a = 0;
+  if (dtype != JJ_F64 && dtype != JJ_C128)
+    a = -1;
+  else if (n < 0)
+    a = -5;
+  else if (m < n)
+    a = -4;
+  else if (n > 0) {
+    if (!G)
+      a = -2;
+    else if (!J)
+      a = -3;
+    else if (ldg < m)
+      a = -6;
+    else if (!lambda)
+      a = -7;
+    else if (!V)
+      a = -8;
+    else if (ldv < m)
+      a = -9;
+    for (int i = 0; a == 0 && i < n; i++)
+      if (J[i] != 1 && J[i] != -1) a = -3;
+  }
+  if (a < 0) {
+    if (info) info->status = a;
+    return a;
+  }
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (n == 0) return 0;
+  jj_opts o;
+  jjacobi_default_opts(&o);
+  if (opts) o = *opts;
+  std::lock_guard<std::mutex> lk(g_mutex);
+  try {
+    return solve_one(dtype, G, J, n, ldg, lambda, V, ldv, tol, max_sweeps, o, info, true, false, m);
+  } catch (const HipFail&) {
+    if (info) info->status = JJ_HIP_ERROR;
+    return JJ_HIP_ERROR;
+  }
+}
+
+int jjacobi_factor(int dtype, const void* H, int n, int ldh, void* G, int ldg, signed char* J, int* rank, double tol,
+                   const jj_opts* opts) {
+  if (dtype != JJ_F64 && dtype != JJ_C128) return -1;
+  if (n < 0) return -3;
+  if (!rank) return -8;
+  *rank = 0;
+  if (n == 0) return 0;
+  if (!H) return -2;
+  if (ldh < n) return -4;
+  if (!G) return -5;
+  if (ldg < n) return -6;
+  if (!J) return -7;
+  jj_opts o;
+  jjacobi_default_opts(&o);
+  if (opts) o = *opts;
+  std::lock_guard<std::mutex> lk(g_mutex);
+  try {
+    hipStream_t stream = lib_stream();
+    StreamJoin join((hipStream_t)o.stream, stream);
+    return bp_factor_dev(dtype, H, n, ldh, (double*)G, ldg, J, rank, tol, stream);
+  } catch (const HipFail&) {
+    return JJ_HIP_ERROR;
+  }
+}
+
+int jjacobi_eigh(int dtype, void* H, int n, int ldh, double* lambda, void* V, int ldv, double tol, int max_sweeps,
+                 const jj_opts* opts, jj_info* info) {
+  if (dtype != JJ_F64 && dtype != JJ_C128) return -1;
+  if (n < 0) return -3;
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (n == 0) return 0;
+  if (!H) return -2;
+  if (ldh < n) return -4;
+  if (!lambda) return -5;
+  if (!V) return -6;
+  if (ldv < n) return -7;
+  jj_opts o;
+  jjacobi_default_opts(&o);
+  if (opts) o = *opts;
+  std::lock_guard<std::mutex> lk(g_mutex);
+  try {
+    const int w = dtype == JJ_C128 ? 2 : 1;
+    std::vector<signed char> J(n);
+    int r = 0;
+    int st;
+    {
+      hipStream_t stream = lib_stream();
+      StreamJoin join((hipStream_t)o.stream, stream);
+      // G overwrites H (H is copied into the workspace first)
+      st = bp_factor_dev(dtype, H, n, ldh, (double*)H, ldh, J.data(), &r, 0.0, stream);
+      if (st == JJ_OK && r < n) {
+        // the zero eigenvalue (multiplicity n - r) at the end; its vectors are not formed
+        ck(hipMemsetAsync(lambda + r, 0, (size_t)(n - r) * sizeof(double), stream), "memset");
+        ck(hipMemset2DAsync((double*)V + (size_t)r * ldv * w, (size_t)ldv * w * sizeof(double), 0,
+                            (size_t)n * w * sizeof(double), n - r, stream),
+           "memset");
+      }
+    }
+    if (st != JJ_OK) {
+      if (info) info->status = st;
+      return st;
+    }
+    if (info) info->rank = r;
+    if (r == 0) return JJ_OK;
+    st = solve_one(dtype, H, J.data(), r, ldh, lambda, V, ldv, tol, max_sweeps, o, info, true, false, n);
+    if (info) info->rank = r;
+    return st;
   } catch (const HipFail&) {
     if (info) info->status = JJ_HIP_ERROR;
     return JJ_HIP_ERROR;

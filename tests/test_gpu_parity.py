@@ -340,3 +340,27 @@ def test_leading_dimensions_and_padding(cplx):
     lref, Vref, _ = gpu_solve(G, J)
     assert np.array_equal(lam.cpu().numpy(), lref)
     assert np.array_equal(Vp[:, :n].cpu().numpy().T, Vref)
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("n", [130, 300, 512])
+def test_three_level_pivots(cplx, n):
+    # block width 64: pivots of up to 128 columns shortened to their Cholesky
+    # factor R and orthogonalised by the blocked block-oriented method on R
+    # (Section 5, Algorithm 5.1); ragged blocks (130: 33 + 33 / 32 + 32 columns,
+    # 300: six blocks of 50) and equal ones (512: eight of 64)
+    G, J, lam = jjgen.make(n, cplx, n // 3, 1e-6, 1.0, seed=5200 + n + 10000 * cplx)
+    lg, V, info = gpu_solve(G, J, block_width=64)
+    assert info["status"] == 0, info
+    assert info["block_width"] > 32
+    check_parity(G, J, lg, "three-level n=%d cplx=%s" % (n, cplx))
+    check_vectors(G, J, lg, V)
+
+
+def test_three_level_config4_law_against_stored_oracle():
+    # workload 4's law at n = 1024 (complex) with block width 64
+    G, J, lam = jjgen.config(4, n=1024)
+    lg, V, info = gpu_solve(G, J, block_width=64)
+    assert info["status"] == 0 and info["block_width"] == 64, info
+    assert np.sum(lg > 0) == np.sum(J > 0)
+    check_stored_parity(lg, "config4_n1024")
