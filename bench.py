@@ -476,6 +476,42 @@ def bench_inner_modes(jj, torch, ks=(3, 2)):
     return out
 
 
+def bench_pairing(jj, torch, ks=(3, 2)):
+    """Round-robin (Section 4.2, the default) against modulus pairing (Section
+    4.1, one more step per sweep) on workloads 3 and 2: time and sweeps of one
+    graph-replayed solve each after a warm-up, block width 32."""
+    import jjgen
+    out = {}
+    for k in ks:
+        G, J, _ = jjgen.config(k)
+        n = G.shape[0]
+        cplx = np.iscomplexobj(G)
+        dev = torch.device("cuda:0")
+        pristine = torch.from_numpy(np.ascontiguousarray(G.T)).to(dev)
+        lam = torch.empty(n, dtype=torch.float64, device=dev)
+        Vt = torch.empty((n, n), dtype=pristine.dtype, device=dev)
+        stream = torch.cuda.current_stream().cuda_stream
+        res = {}
+        for name, strat in (("round_robin", 0), ("modulus", 1)):
+            o = jj.make_opts(stream=stream, block_width=32, strategy=strat)
+            for rep in range(2):
+                Gw = pristine.clone()
+                info = jj.jj_info()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st = jj.jjacobi_solve_ex(jj.JJ_C128 if cplx else jj.JJ_F64, Gw.data_ptr(), J, n, n, lam.data_ptr(),
+                                         Vt.data_ptr(), n, 0.0, 0, o, info)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                if st != 0:
+                    raise RuntimeError("workload %d strategy %d: status %d" % (k, strat, st))
+            res[name] = dict(seconds=dt, sweeps=info.sweeps, ms_per_sweep=1e3 * dt / max(1, info.sweeps))
+            note("workload %d %s pairing: %.1f ms, %d sweeps" % (k, name, 1e3 * dt, info.sweeps))
+        res["modulus_over_round_robin_time"] = res["modulus"]["seconds"] / res["round_robin"]["seconds"]
+        out["config%d" % k] = res
+    return out
+
+
 def stored_long_oracle(k):
     """Long-double oracle eigenvalues of workload k (the adjudicator), or None."""
     path = os.path.join(ROOT, "tests", "golden", "config%d_lambda_long.txt" % k)
@@ -503,7 +539,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--block-width", type=int, default=0, help="0: library choice (tuned)")
-    ap.add_argument("--inner-mode", type=int, default=0)
+    ap.add_argument("--inner-mode", type=int, default=-1, help="-1: library choice")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -608,7 +644,7 @@ def main():
         "config": {"workload": "blocked real symmetric indefinite n=4096 float64, J with 3000 positive, "
                                "|lambda| log-uniform [1e-12, 1], plain FP64",
                    "n": n, "block_width": timed_infos[-1]["block_width"], "nblocks": timed_infos[-1]["nblocks"],
-                   "pairing": "round-robin", "inner_mode": args.inner_mode},
+                   "pairing": "round-robin", "inner_mode": timed_infos[-1]["inner_mode"]},
         "sweeps": sweeps,
         "ms_per_sweep": ms_step / (sum(sweeps) / len(sweeps)),
         "c_time_model": (dt / K) / n ** 3,
@@ -658,6 +694,8 @@ def main():
     if not args.no_inner_modes:
         note("pivot variants (block-oriented / full) on workloads 3 and 2")
         out["inner_modes"] = bench_inner_modes(jj, torch)
+        note("pairing strategies (round-robin / modulus) on workloads 3 and 2")
+        out["pairing"] = bench_pairing(jj, torch)
     if not args.no_batched:
         note("batched leg")
         out["batched"] = bench_batched(jj, torch, args.batch_count, args.loop_sample)

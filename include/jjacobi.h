@@ -63,21 +63,27 @@ extern "C" {
 /* Options.  Zero-initialised fields select the defaults noted. */
 typedef struct jj_opts {
   void* stream;          /* hipStream_t to order the work on; NULL: null stream */
-  int block_width;       /* target block width n_t of eq. 3.2 (at most 32); 0: library
-                            choice: 32, or the faster of 16 and 32 timed over two sweeps
-                            (each after one untimed sweep) on the first problem of each
-                            (dtype, size) class seen by the process: single solves with
+  int block_width;       /* target block width n_t of eq. 3.2: at most 32, or 64 for
+                            three-level pivots (Section 5; plain FP64, block-oriented, no
+                            diagonal pass; otherwise 32 is used); 0: library choice: 32, or
+                            the fastest candidate (16, 32, and 64 for single solves) on the
+                            first problem of each (dtype, size) class seen by the process,
+                            timed over a whole solve up to n = 2048 and over two sweeps
+                            above (each after one untimed sweep): single solves with
                             n >= 1024, every batched problem with n > 64 */
   int inner_max_sweeps;  /* cap on inner sweeps of one pivot solve (Algorithm 3.2 max_it);
                             0: 12 */
   int diag_pass;         /* diagonal-block pre-processing (Algorithm 3.3, first inner loop):
                             0: off (default), 1: first sweep only, 2: every sweep */
-  int inner_mode;        /* 0 (default): block-oriented (Section 3.4, Algorithm 5.1): the
+  int inner_mode;        /* 0: block-oriented (Section 3.4, Algorithm 5.1): the
                                first step of a sweep makes one full inner pass per
                                pivot, the other steps one pass over the off-diagonal
                                block;
                             1: full pivot diagonalisation (full block, Section 3.3),
-                               up to inner_max_sweeps inner sweeps */
+                               up to inner_max_sweeps inner sweeps;
+                            -1 (jjacobi_default_opts): library choice: tuned together
+                               with the block width where the width is tuned (whole
+                               solves of both variants up to n = 1024), else 0 */
   int precision;         /* 0: FP64 throughout; 1: mixed (FP32 Gram in pre-sweeps) */
   double mixed_switch;   /* mixed: sweeps whose max scaled off-diagonal is below this
                             run in FP64; 0: 1e-5 */
@@ -107,27 +113,35 @@ typedef struct jj_info {
                               Gram checks of the last sweep */
   double seconds;          /* wall-clock time of the solve */
   int mixed_sweeps;        /* sweeps that used the FP32 Gram (precision 1) */
-  int mixed_resolved;      /* pivot solves of those sweeps redone from an FP64 Gram block
-                              because the FP32 block could not be factored */
+  int mixed_resolved;      /* pairs of blocks whose FP32 Gram block could not be factored
+                              in those sweeps; each is left for that sweep and formed
+                              and solved in FP64 in the later mixed sweeps */
   int rank;                /* jjacobi_eigh: rank of H found by the front end */
-  int reserved[5];
+  int inner_mode;          /* inner mode used (0 block-oriented, 1 full) */
+  int reserved[4];
 } jj_info;
 
 /* Fill *opts with the defaults. */
 void jjacobi_default_opts(jj_opts* opts);
 
-/* Real symmetric H = G J G^T, G float64 (n x n, leading dimension ldg).
- * lambda: n doubles; V: n x n doubles, leading dimension n. */
+/* Real symmetric H = G J G^T, G float64 (n x n, leading dimension ldg), by the
+ * blocked one-sided J-Jacobi process (Sections 3.3-3.4 and 5.3, Algorithm 5.2
+ * on one device): lambda_i = j_i ||g~_i||^2, v_i = g~_i / ||g~_i|| (eq. 2.10-2.11).
+ * lambda: n doubles; V: n x n doubles, leading dimension n.  Default options. */
 int jjacobi_solve(double* G, const signed char* J, int n, int ldg, double* lambda, double* V,
                   double tol, int max_sweeps);
 
-/* Complex Hermitian H = G J G^*, G complex128 interleaved (n x n, ldg).
- * lambda: n doubles; V: n x n complex128, leading dimension n. */
+/* Complex Hermitian H = G J G^*, G complex128 interleaved (n x n, ldg): the
+ * same process with complex rotations (eq. 2.3 and the complex hyperbolic
+ * rotations of Section 2.3).  lambda: n doubles; V: n x n complex128, leading
+ * dimension n.  Default options. */
 int jjacobi_zsolve(void* G, const signed char* J, int n, int ldg, double* lambda, void* V,
                    double tol, int max_sweeps);
 
-/* General form: dtype JJ_F64 or JJ_C128, V with leading dimension ldv >= n,
- * options (nullable: defaults) and report (nullable). */
+/* General form of the two above (Sections 2.3, 3 and 5): dtype JJ_F64 or
+ * JJ_C128, V with leading dimension ldv >= n, options (nullable: defaults;
+ * the pivot variants of Sections 3.3/3.4, the pairings of Section 4, the
+ * diagonal-block pass of Algorithm 3.3) and report (nullable). */
 int jjacobi_solve_ex(int dtype, void* G, const signed char* J, int n, int ldg, double* lambda,
                      void* V, int ldv, double tol, int max_sweeps, const jj_opts* opts,
                      jj_info* info);
@@ -196,7 +210,9 @@ int jjacobi_factor(int dtype, const void* H, int n, int ldh, void* G, int ldg, s
 int jjacobi_eigh(int dtype, void* H, int n, int ldh, double* lambda, void* V, int ldv, double tol,
                  int max_sweeps, const jj_opts* opts, jj_info* info);
 
-/* Many independent problems in one call (problem k uses dtype[k], G[k], J[k],
+/* Many independent problems in one call, each solved by the process of
+ * jjacobi_solve_ex (the problems share launches; not a form the paper states)
+ * (problem k uses dtype[k], G[k], J[k],
  * n[k], ldg[k], lambda[k], V[k], ldv[k]; all device pointers except J[k]).
  * info: array of count reports, or NULL.  Returns the largest status over the
  * problems (a negative value if an argument is invalid; then nothing runs). */
@@ -226,7 +242,8 @@ typedef struct jj_profile {
   int n, nblocks, block_width, sweeps, dtype, valid;
 } jj_profile;
 
-/* Copy the profile of the last profiled solve of this thread into *out.
+/* Copy the profile of the last profiled solve of this thread into *out (the
+ * per-kernel time of the steps of Section 5.3).
  * Returns 0, or -1 if there is none (out untouched) or out is NULL. */
 int jjacobi_last_profile(jj_profile* out);
 

@@ -22,7 +22,7 @@ class jj_info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("sweeps", ctypes.c_int), ("block_width", ctypes.c_int),
                 ("nblocks", ctypes.c_int), ("pivots_rotated", ctypes.c_longlong), ("final_offdiag", ctypes.c_double),
                 ("seconds", ctypes.c_double), ("mixed_sweeps", ctypes.c_int), ("mixed_resolved", ctypes.c_int),
-                ("rank", ctypes.c_int), ("reserved", ctypes.c_int * 5)]
+                ("rank", ctypes.c_int), ("inner_mode", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

@@ -158,6 +158,13 @@ void launch_gram_f32mix(const double* G, int ldg, int n, const PivotList& pl, in
                         double* part, hipStream_t stream, const Batch& b = Batch());
 void launch_gram_c64mix(const double* G, int ldg, int n, const PivotList& pl, int nch, int rows_per_chunk,
                         double* part, hipStream_t stream, const Batch& b = Batch());
+// Mixed-precision sweeps: one launch whose slots choose their precision, FP64
+// for a single-solve slot with f64[slot] set or a batched slot whose problem
+// has left its FP32 sweeps (b.prec[problem] == 0), FP32 MFMA otherwise.
+void launch_gram_sel(bool cplx, const double* G, int ldg, int n, const PivotList& pl, int nch, int rows_per_chunk,
+                     double* part, hipStream_t stream, const Batch& b, const int* f64);
+// p[0..count) = v
+void launch_fill_int(int* p, int count, int v, hipStream_t stream);
 
 // Per pivot: sum the Gram partials, test convergence, Cholesky, inner one-sided
 // J-Jacobi on R accumulating W_P.  W[p] (kMaxPivot x kMaxPivot, column-major,
@@ -171,14 +178,16 @@ void launch_gram_c64mix(const double* G, int ldg, int n, const PivotList& pl, in
 // inner_max inner sweeps, and the rotated columns are written back to G (G, ldg;
 // rotflag 0, pivots_rotated counts the pivot if its last inner sweep rotated).
 // Only the first ceil(n / rows_per_chunk) partials of a pivot are summed.
-// refine (nullable, single problems): refine[p] is set to 1 for a pivot that
-// failed softly and to 0 otherwise.  only (nullable): pivots with only[p] == 0
-// return at once (a re-solve of the flagged pivots).
+// refine (nullable, single problems in mixed sweeps): per-pair flags kept
+// across sweeps; a pivot that fails softly sets its flag (and is left for this
+// sweep), and a flagged pivot (its Gram block formed in FP64, see
+// launch_gram_sel) is solved with tol64 and no soft failure.  only (nullable):
+// pivots with only[p] == 0 return at once.
 void launch_pivot_f64(const double* part, int nch, int n, int rows_per_chunk, const PivotList& pl, double tol,
-                      int inner_max, int inner_mode, int soft, double* W, int* rotflag, SweepStats* st,
+                      double tol64, int inner_max, int inner_mode, int soft, double* W, int* rotflag, SweepStats* st,
                       hipStream_t stream, const Batch& b, int* refine, const int* only, double* G, int ldg);
 void launch_pivot_c128(const double* part, int nch, int n, int rows_per_chunk, const PivotList& pl, double tol,
-                       int inner_max, int inner_mode, int soft, double* W, int* rotflag, SweepStats* st,
+                       double tol64, int inner_max, int inner_mode, int soft, double* W, int* rotflag, SweepStats* st,
                        hipStream_t stream, const Batch& b, int* refine, const int* only, double* G, int ldg);
 
 // [G_i G_j] <- [G_i G_j] W_P in place for pivots with rotflag set.

@@ -79,15 +79,10 @@ constexpr int kGramRows = 64;
 constexpr int kGramLdc = 68;
 
 template <bool F32>
-__global__ __launch_bounds__(256, 2) void k_gram_real(const double* __restrict__ G0, int ldg0, int n0,
-                                                     const int* __restrict__ cols, const int* __restrict__ mlist,
-                                                     int rows_per_chunk, double* __restrict__ part, Batch bt,
-                                                     const int* __restrict__ only) {
-  __shared__ double smem[2 * kMaxPivot * kGramLdc];  // two staged blocks; then the wave reduction
-  const int nch = gridDim.x;
-  int slot, ch;
-  xcd_slot_chunk(slot, ch);
-  if (only != nullptr && !only[slot]) return;  // a re-solve launch: this pivot was solved
+__device__ __forceinline__ void gram_real_body(const double* __restrict__ G0, int ldg0, int n0,
+                                               const int* __restrict__ cols, const int* __restrict__ mlist,
+                                               int rows_per_chunk, double* __restrict__ part, const Batch& bt,
+                                               int slot, int ch, int nch, double* smem) {
   int p = slot, ldg = ldg0, n = n0;
   double* Gm = const_cast<double*>(G0);
   SweepStats* stp = nullptr;
@@ -187,6 +182,40 @@ __global__ __launch_bounds__(256, 2) void k_gram_real(const double* __restrict__
         t++;
       }
   }
+}
+
+template <bool F32>
+__global__ __launch_bounds__(256, 2) void k_gram_real(const double* __restrict__ G0, int ldg0, int n0,
+                                                     const int* __restrict__ cols, const int* __restrict__ mlist,
+                                                     int rows_per_chunk, double* __restrict__ part, Batch bt,
+                                                     const int* __restrict__ only) {
+  __shared__ double smem[2 * kMaxPivot * kGramLdc];  // two staged blocks; then the wave reduction
+  int slot, ch;
+  xcd_slot_chunk(slot, ch);
+  if (only != nullptr && !only[slot]) return;  // a re-solve launch: this pivot was solved
+  gram_real_body<F32>(G0, ldg0, n0, cols, mlist, rows_per_chunk, part, bt, slot, ch, gridDim.x, smem);
+}
+
+// Mixed-precision sweeps: the precision of each slot's Gram block chosen in
+// the kernel, FP64 for a single-solve slot whose flag f64[slot] is set (a pair
+// whose FP32 block could not be factored earlier in the solve) and for a
+// batched slot whose problem has left its FP32 sweeps, FP32 MFMA otherwise.
+__device__ __forceinline__ bool gram_slot_f64(const Batch& bt, int slot, const int* f64) {
+  if (bt.slot_prob != nullptr) return bt.prec == nullptr || !bt.prec[bt.slot_prob[slot]];
+  return f64 != nullptr && f64[slot];
+}
+
+__global__ __launch_bounds__(256, 2) void k_gram_real_sel(const double* __restrict__ G0, int ldg0, int n0,
+                                                         const int* __restrict__ cols, const int* __restrict__ mlist,
+                                                         int rows_per_chunk, double* __restrict__ part, Batch bt,
+                                                         const int* __restrict__ f64) {
+  __shared__ double smem[2 * kMaxPivot * kGramLdc];
+  int slot, ch;
+  xcd_slot_chunk(slot, ch);
+  if (gram_slot_f64(bt, slot, f64))
+    gram_real_body<false>(G0, ldg0, n0, cols, mlist, rows_per_chunk, part, bt, slot, ch, gridDim.x, smem);
+  else
+    gram_real_body<true>(G0, ldg0, n0, cols, mlist, rows_per_chunk, part, bt, slot, ch, gridDim.x, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -339,15 +368,10 @@ __device__ __forceinline__ void gram3m_store(double* __restrict__ out, int nt, i
 }
 
 template <bool F32>
-__global__ __launch_bounds__(256, 2) void k_gram_cplx(const double* __restrict__ G0, int ldg0, int n0,
-                                                     const int* __restrict__ cols, const int* __restrict__ mlist,
-                                                     int rows_per_chunk, double* __restrict__ part, Batch bt,
-                                                     const int* __restrict__ only) {
-  __shared__ dv2 smem[2 * kMaxPivot * kGramLdcC];  // two staged blocks; then the wave reduction
-  const int nch = gridDim.x;
-  int slot, ch;
-  xcd_slot_chunk(slot, ch);
-  if (only != nullptr && !only[slot]) return;  // a re-solve launch: this pivot was solved
+__device__ __forceinline__ void gram_cplx_body(const double* __restrict__ G0, int ldg0, int n0,
+                                               const int* __restrict__ cols, const int* __restrict__ mlist,
+                                               int rows_per_chunk, double* __restrict__ part, const Batch& bt,
+                                               int slot, int ch, int nch, dv2* smem) {
   int p = slot, ldg = ldg0, n = n0;
   double* Gm = const_cast<double*>(G0);
   SweepStats* stp = nullptr;
@@ -459,6 +483,31 @@ __global__ __launch_bounds__(256, 2) void k_gram_cplx(const double* __restrict__
     else
       gram3m_store<1, F32>(out, nt, c16, g, q1, q2, q3);
   }
+}
+
+template <bool F32>
+__global__ __launch_bounds__(256, 2) void k_gram_cplx(const double* __restrict__ G0, int ldg0, int n0,
+                                                     const int* __restrict__ cols, const int* __restrict__ mlist,
+                                                     int rows_per_chunk, double* __restrict__ part, Batch bt,
+                                                     const int* __restrict__ only) {
+  __shared__ dv2 smem[2 * kMaxPivot * kGramLdcC];  // two staged blocks; then the wave reduction
+  int slot, ch;
+  xcd_slot_chunk(slot, ch);
+  if (only != nullptr && !only[slot]) return;  // a re-solve launch: this pivot was solved
+  gram_cplx_body<F32>(G0, ldg0, n0, cols, mlist, rows_per_chunk, part, bt, slot, ch, gridDim.x, smem);
+}
+
+__global__ __launch_bounds__(256, 2) void k_gram_cplx_sel(const double* __restrict__ G0, int ldg0, int n0,
+                                                         const int* __restrict__ cols, const int* __restrict__ mlist,
+                                                         int rows_per_chunk, double* __restrict__ part, Batch bt,
+                                                         const int* __restrict__ f64) {
+  __shared__ dv2 smem[2 * kMaxPivot * kGramLdcC];
+  int slot, ch;
+  xcd_slot_chunk(slot, ch);
+  if (gram_slot_f64(bt, slot, f64))
+    gram_cplx_body<false>(G0, ldg0, n0, cols, mlist, rows_per_chunk, part, bt, slot, ch, gridDim.x, smem);
+  else
+    gram_cplx_body<true>(G0, ldg0, n0, cols, mlist, rows_per_chunk, part, bt, slot, ch, gridDim.x, smem);
 }
 
 // Update, complex: D^T = W^T X^T with Re = Wr^T Xr^T - Wi^T Xi^T and
@@ -669,6 +718,25 @@ void launch_gram_c64mix(const double* G, int ldg, int n, const PivotList& pl, in
                         double* part, hipStream_t stream, const Batch& b) {
   launch(k_gram_cplx<true>, dim3(nch, pl.count), dim3(256), 0, stream, G, ldg, n, pl.cols, pl.m, rows_per_chunk,
          part, b, (const int*)nullptr);
+}
+
+void launch_gram_sel(bool cplx, const double* G, int ldg, int n, const PivotList& pl, int nch, int rows_per_chunk,
+                     double* part, hipStream_t stream, const Batch& b, const int* f64) {
+  if (cplx)
+    launch(k_gram_cplx_sel, dim3(nch, pl.count), dim3(256), 0, stream, G, ldg, n, pl.cols, pl.m, rows_per_chunk, part,
+           b, f64);
+  else
+    launch(k_gram_real_sel, dim3(nch, pl.count), dim3(256), 0, stream, G, ldg, n, pl.cols, pl.m, rows_per_chunk, part,
+           b, f64);
+}
+
+__global__ void k_fill_int(int* p, int count, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
+void launch_fill_int(int* p, int count, int v, hipStream_t stream) {
+  if (count > 0) launch(k_fill_int, dim3((count + 255) / 256), dim3(256), 0, stream, p, count, v);
 }
 
 void launch_update_c128(double* G, int ldg, int n, const PivotList& pl, const double* W, const int* rotflag,

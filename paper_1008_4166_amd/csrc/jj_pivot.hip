@@ -376,7 +376,8 @@ template <bool CPLX, int LPS, bool DENSE, int CHOL>
 __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE ? 4 : 1, 8))) void k_pivot(const double* __restrict__ part, int nch, int n0,
                                                     int rows_per_chunk, const int* __restrict__ mlist,
                                                     const int* __restrict__ nfirst,
-                                                    const signed char* __restrict__ sgl, double tol, int inner_max,
+                                                    const signed char* __restrict__ sgl, double tol, double tol64,
+                                                    int inner_max,
                                                     int mode, int soft, double* __restrict__ Wout,
                                                     int* __restrict__ rotflag, SweepStats* st0, Batch bt,
                                                     int* __restrict__ refine, const int* __restrict__ only,
@@ -416,7 +417,13 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
   const int m = mlist[p];
   const int n1 = nfirst[p], n2 = m - n1;
   if (tid < kMaxPivot) s_sg[tid] = sgl[p * kMaxPivot + tid];
-  if (refine != nullptr && tid == 0) refine[bslot] = 0;
+  // single-solve mixed sweeps: a pair whose FP32 block could not be factored
+  // earlier in the solve has its Gram block formed in FP64 from then on (flag
+  // refine[slot], kept across sweeps) and is solved as in an FP64 sweep
+  if (refine != nullptr && refine[bslot]) {
+    soft = 0;
+    tol = tol64;
+  }
   const signed char* sg = s_sg;  // signs of the pivot's columns, in LDS
 
   if (mode == 3) {
@@ -931,8 +938,8 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
     }
   }
   if (s_bad && soft && refine != nullptr) {
-    // handed on to the FP64 re-solve of this step, which writes W_P, the flag
-    // and the counters of this pivot
+    // left as it is in this sweep: the pair is solved from an FP64 Gram block
+    // from the next sweep on
     if (tid == 0) rotflag[bslot] = 0;
     return;
   }
@@ -979,29 +986,29 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
 constexpr int kPivotLPS = 8;
 
 void launch_pivot_f64(const double* part, int nch, int n, int rows_per_chunk, const PivotList& pl, double tol,
-                      int inner_max, int inner_mode, int soft, double* W, int* rotflag, SweepStats* st,
+                      double tol64, int inner_max, int inner_mode, int soft, double* W, int* rotflag, SweepStats* st,
                       hipStream_t stream, const Batch& b, int* refine, const int* only, double* G, int ldg) {
   // batched launches: two workgroups per CU, lane-read Cholesky (register budget)
   if (b.slot_prob != nullptr)
     launch((k_pivot<false, kPivotLPS, true, 0>), dim3(pl.count), dim3(64 * kPivotLPS), 0, stream, part, nch, n,
-           rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st, b, refine, only,
+           rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, tol64, inner_max, inner_mode, soft, W, rotflag, st, b, refine, only,
            G, ldg, pl.cols);
   // full diagonalisation (mode 0, several inner sweeps): the lane-read Cholesky
   else if ((inner_mode == 0 && inner_max > 1) || inner_mode == 3)
     launch((k_pivot<false, kPivotLPS, false, 0>), dim3(pl.count), dim3(64 * kPivotLPS), 0, stream, part, nch, n,
-           rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st, b, refine, only,
+           rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, tol64, inner_max, inner_mode, soft, W, rotflag, st, b, refine, only,
            G, ldg, pl.cols);
   else
     launch((k_pivot<false, kPivotLPS, false, 1>), dim3(pl.count), dim3(64 * kPivotLPS), 0, stream, part, nch, n,
-           rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st, b, refine, only,
+           rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, tol64, inner_max, inner_mode, soft, W, rotflag, st, b, refine, only,
            G, ldg, pl.cols);
 }
 
 void launch_pivot_c128(const double* part, int nch, int n, int rows_per_chunk, const PivotList& pl, double tol,
-                       int inner_max, int inner_mode, int soft, double* W, int* rotflag, SweepStats* st,
+                       double tol64, int inner_max, int inner_mode, int soft, double* W, int* rotflag, SweepStats* st,
                        hipStream_t stream, const Batch& b, int* refine, const int* only, double* G, int ldg) {
   launch((k_pivot<true, kPivotLPS, false, 2>), dim3(pl.count), dim3(64 * kPivotLPS), 0, stream, part, nch, n,
-                     rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, inner_max, inner_mode, soft, W, rotflag, st, b, refine, only,
+                     rows_per_chunk, pl.m, pl.nfirst, pl.sg, tol, tol64, inner_max, inner_mode, soft, W, rotflag, st, b, refine, only,
            G, ldg, pl.cols);
 }
 

@@ -454,6 +454,7 @@ struct StreamJoin {
 
 // Block width chosen per (dtype, size bucket) by timing two sweeps of each
 // candidate on the first problem of that bucket (see tune_block_width).
+// value: block width * 2 + inner mode (0 block-oriented, 1 full diagonalisation)
 static std::map<std::pair<int, int>, int> g_tuned_bw;
 static int size_bucket(int n) {
   int b = 0;
@@ -461,14 +462,24 @@ static int size_bucket(int n) {
   return b;  // 0: n <= 64, 1: <= 128, 2: <= 256, ...
 }
 static int tune_block_width(int dtype, void* G, const signed char* J, int n, int ldg, hipStream_t stream,
-                            bool wide);
+                            bool wide, bool modes);
 // wide: 64 (three-level pivots) is a candidate too (single solves; the batched
-// form takes at most 32); cached separately
+// form takes at most 32); modes: the full-diagonalisation variant too (single
+// solves that leave the inner mode to the library).  Cached per (dtype, wide,
+// modes, size bucket).  Returns block width * 2 + inner mode.
 static int tuned_block_width(int dtype, void* G, const signed char* J, int n, int ldg, hipStream_t stream,
-                             bool wide = false) {
-  const auto key = std::make_pair(dtype + (wide ? 2 : 0), size_bucket(n));
+                             bool wide = false, bool modes = false) {
+  modes = modes && n <= 1024;  // the candidate set is what keys the cache
+  const auto key = std::make_pair(dtype + (wide ? 2 : 0) + (modes ? 4 : 0), size_bucket(n));
   auto it = g_tuned_bw.find(key);
-  if (it == g_tuned_bw.end()) it = g_tuned_bw.emplace(key, tune_block_width(dtype, G, J, n, ldg, stream, wide)).first;
+  if (it == g_tuned_bw.end() && !wide) {
+    // a choice among more candidates that did not pick width 64 is the choice
+    // among these
+    auto w = g_tuned_bw.find(std::make_pair(dtype + 2 + (modes ? 4 : 0), size_bucket(n)));
+    if (w != g_tuned_bw.end() && (w->second >> 1) != 64) it = g_tuned_bw.emplace(key, w->second).first;
+  }
+  if (it == g_tuned_bw.end())
+    it = g_tuned_bw.emplace(key, tune_block_width(dtype, G, J, n, ldg, stream, wide, modes)).first;
   return it->second;
 }
 
@@ -492,11 +503,18 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
   // block width: the caller's, else tuned for large problems (first use of a
   // size bucket), else 32
   // (widths above 32 make three-level pivots: plain FP64, block-oriented, no
-  // diagonal pass, one step at a time; other option sets take 32)
-  const bool three_ok = o.precision == 0 && o.diag_pass == 0 && o.inner_mode == 0 && o.step_groups <= 1;
+  // diagonal pass, one step at a time; other option sets take 32).  The inner
+  // mode: the caller's, or (inner_mode < 0) tuned with the width where the
+  // width is tuned, else block-oriented.
+  int imode = o.inner_mode;
+  const bool three_ok = o.precision == 0 && o.diag_pass == 0 && imode <= 0 && o.step_groups <= 1;
   int nt = o.block_width > 0 ? std::min(o.block_width, three_ok ? 2 * kMaxBlock : kMaxBlock) : 32;
-  if (o.block_width <= 0 && graphs_ok && m == n && n >= 1024)
-    nt = tuned_block_width(dtype, Gv, J, n, ldg, stream, three_ok);
+  if (o.block_width <= 0 && graphs_ok && m == n && n >= 1024) {
+    const int tv = tuned_block_width(dtype, Gv, J, n, ldg, stream, three_ok, imode < 0);
+    nt = tv >> 1;
+    if (imode < 0) imode = tv & 1;
+  }
+  if (imode < 0) imode = 0;
   const int inner_max = o.inner_max_sweeps > 0 ? o.inner_max_sweeps : 12;
   if (tol <= 0.0) tol = (double)m * std::ldexp(1.0, -53);
   if (max_sweeps <= 0) max_sweeps = 100;
@@ -546,7 +564,7 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
     c.take<double>((size_t)nb_piv * nch * kMaxPivot * kMaxPivot * (cplx ? 2 : 1));
     c.take<double>((size_t)nb_piv * kMaxPivot * kMaxPivot * (cplx ? 2 : 1));
     c.take<int>(nb_piv);
-    c.take<int>(nb_piv);
+    c.take<int>((size_t)std::max(P.nsteps, 1) * h + P.nbl);
     c.take<SweepStats>(1);
     c.take<int>(n);
     c.take<signed char>(n);
@@ -583,7 +601,10 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
   double* d_part = c.take<double>((size_t)nb_piv * nch * kMaxPivot * kMaxPivot * (cplx ? 2 : 1));
   double* d_W = c.take<double>((size_t)nb_piv * kMaxPivot * kMaxPivot * (cplx ? 2 : 1));
   int* d_rot = c.take<int>(nb_piv);
-  int* d_refine = c.take<int>(nb_piv);  // mixed sweeps: pivots to re-solve from an FP64 Gram block
+  // mixed sweeps: per (step, pair), then per diagonal block, 1 once the pair's
+  // FP32 Gram block could not be factored (its Gram block is FP64 from then on)
+  int* d_promote = c.take<int>((size_t)std::max(P.nsteps, 1) * h + P.nbl);
+  int* d_promote_diag = d_promote + (size_t)std::max(P.nsteps, 1) * h;
   SweepStats* d_st = c.take<SweepStats>(1);
   int* d_colmap = c.take<int>(n);
   signed char* d_sgn = c.take<signed char>(n);
@@ -646,6 +667,7 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
   size_t e0 = prof.mark();
   launch_reset_stats(d_st, stream);
   launch_check_finite(G, ldg, m, n, cplx, d_st, stream);
+  launch_fill_int(d_promote, (int)((size_t)std::max(P.nsteps, 1) * h + P.nbl), 0, stream);
   prof.done(JJ_K_OTHER, e0, 0);
   ck(hipGetLastError(), "launch");
   ck(hipMemcpyAsync(&hst, d_st, sizeof(hst), hipMemcpyDeviceToHost, stream), "D2H");
@@ -660,7 +682,6 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
   }
 
   auto gram64 = cplx ? launch_gram_c128 : launch_gram_f64;
-  auto gram32 = cplx ? launch_gram_c64mix : launch_gram_f32mix;
   auto pivot = cplx ? launch_pivot_c128 : launch_pivot_f64;
   auto update = cplx ? launch_update_c128 : launch_update_f64;
 
@@ -681,31 +702,24 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
   // eagerly with per-kernel events; otherwise each variant (precision, diagonal
   // pass) is captured once per solve as a HIP graph and replayed per sweep.
   // Gram block and pivot solve of the pairs in pl.  In a mixed sweep the Gram
-  // block is formed on FP32 MFMA and a pivot whose FP32 block cannot be
-  // factored (its scaled condition is beyond FP32, e.g. nearly parallel
-  // columns) is flagged and solved again, within the same step, from an FP64
-  // Gram block: the launches of that re-solve skip every unflagged pivot.
-  auto gram_pivot = [&](bool use_mix, const PivotList& pl, double* part, double* W, int* rot, int* refine,
+  // block is formed on FP32 MFMA, except for the pairs flagged in promote
+  // (their FP32 block could not be factored in an earlier sweep: its scaled
+  // condition is beyond FP32, e.g. nearly parallel columns), which are formed
+  // and solved in FP64; a pivot whose FP32 block cannot be factored is left
+  // for this sweep and flagged.
+  auto gram_pivot = [&](bool use_mix, const PivotList& pl, double* part, double* W, int* rot, int* promote,
                         int mode, int imax, const std::function<void()>& after_first = nullptr) {
     size_t k0 = prof.arm();
     if (use_mix)
-      gram32(G, ldg, m, pl, nch, rows_g, part, stream, Batch());
+      launch_gram_sel(cplx != 0, G, ldg, m, pl, nch, rows_g, part, stream, Batch(), promote);
     else
       gram64(G, ldg, m, pl, nch, rows_g, part, stream, Batch(), nullptr);
     prof.done_kernel(JJ_K_GRAM, k0, pl.count);
     if (after_first) after_first();
     k0 = prof.arm();
-    pivot(part, nch, m, rows_g, pl, use_mix ? tol_mix : tol, imax, mode, use_mix, W, rot, d_st, stream, Batch(),
-          use_mix ? refine : nullptr, nullptr, G, ldg);
+    pivot(part, nch, m, rows_g, pl, use_mix ? tol_mix : tol, tol, imax, mode, use_mix, W, rot, d_st, stream, Batch(),
+          use_mix ? promote : nullptr, nullptr, G, ldg);
     prof.done_kernel(JJ_K_PIVOT, k0, pl.count);
-    if (use_mix) {
-      k0 = prof.arm();
-      gram64(G, ldg, m, pl, nch, rows_g, part, stream, Batch(), refine);
-      prof.done_kernel(JJ_K_GRAM, k0, 0);
-      k0 = prof.arm();
-      pivot(part, nch, m, rows_g, pl, tol, imax, mode, 0, W, rot, d_st, stream, Batch(), nullptr, refine, G, ldg);
-      prof.done_kernel(JJ_K_PIVOT, k0, 0);
-    }
   };
   auto enqueue_sweep = [&](bool use_mix, bool diag) {
     size_t k0 = prof.mark();
@@ -713,7 +727,7 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
     prof.done(JJ_K_OTHER, k0, 0);
     if (diag) {
       PivotList dl{d_dcols, d_dsg, d_dm, d_dnf, P.nbl};
-      gram_pivot(use_mix, dl, d_part, d_W, d_rot, d_refine, 0, inner_max);
+      gram_pivot(use_mix, dl, d_part, d_W, d_rot, d_promote_diag, 0, inner_max);
       k0 = prof.arm();
       update(G, ldg, m, dl, d_W, d_rot, rows_u, stream, Batch(), 0);
       prof.done_kernel(JJ_K_UPDATE, k0, 0);
@@ -742,7 +756,7 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
         gram64(d_RW, kMaxPivot3, kMaxPivot3, ilR, 1, kMaxPivot3, d_ipart, stream, Batch(), nullptr);
         prof.done_kernel(JJ_K_GRAM, k0, 0);
         k0 = prof.arm();
-        pivot(d_ipart, 1, kMaxPivot3, kMaxPivot3, ilR, tol, 1, sidx == 0 ? 0 : 1, 0, d_iW, d_irot, d_st, stream,
+        pivot(d_ipart, 1, kMaxPivot3, kMaxPivot3, ilR, tol, tol, 1, sidx == 0 ? 0 : 1, 0, d_iW, d_irot, d_st, stream,
               Batch(), nullptr, nullptr, d_RW, kMaxPivot3);
         prof.done_kernel(JJ_K_PIVOT, k0, ilR.count);
         k0 = prof.arm();
@@ -762,10 +776,10 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
       // steps one pass over the off-diagonal block only.  With two blocks the
       // single pivot is the whole matrix, and it is diagonalised in full
       // (Section 3.3) instead of one pass per sweep.
-      const bool block_oriented = o.inner_mode == 0 && P.nbl > 2;
+      const bool block_oriented = imode == 0 && P.nbl > 2;
       const int mode = (block_oriented && t > 0) ? 1 : 0;  // kernel mode 1: off-diagonal pass only
       const int imax = block_oriented ? 1 : inner_max;
-      gram_pivot(use_mix, pl, d_part, d_W, d_rot, d_refine, mode, imax);
+      gram_pivot(use_mix, pl, d_part, d_W, d_rot, d_promote + (size_t)t * h, mode, imax);
       k0 = prof.arm();
       update(G, ldg, m, pl, d_W, d_rot, rows_u, stream, Batch(), 0);
       prof.done_kernel(JJ_K_UPDATE, k0, 0);
@@ -801,7 +815,7 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
     launch_reset_stats(d_st, stream);
     *reset = last_node();
     std::vector<int> owner(P.nbl, -1);  // last task to touch each block
-    auto run_task = [&](const std::vector<int>& blocks, PivotList pl, size_t s0, int mode, int imax) {
+    auto run_task = [&](const std::vector<int>& blocks, PivotList pl, size_t s0, int mode, int imax, int* promote) {
       Task tk;
       for (int b : blocks)
         if (owner[b] >= 0) tk.deps.push_back(owner[b]);
@@ -810,7 +824,7 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
       double* part = d_part + s0 * nch * kMaxPivot * kMaxPivot * wsz;
       double* W = d_W + s0 * kMaxPivot * kMaxPivot * wsz;
       int* rot = d_rot + s0;
-      gram_pivot(use_mix, pl, part, W, rot, d_refine + s0, mode, imax, [&]() { tk.first = last_node(); });
+      gram_pivot(use_mix, pl, part, W, rot, promote + s0, mode, imax, [&]() { tk.first = last_node(); });
       update(G, ldg, m, pl, W, rot, rows_u, stream, Batch(), 0);
       tk.last = last_node();
       for (int b : blocks) owner[b] = (int)tasks.size();
@@ -824,10 +838,10 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
         std::vector<int> blocks;
         for (int l = s0; l < s0 + cnt; l++) blocks.push_back(l);
         PivotList dl{d_dcols + (size_t)s0 * kMaxPivot, d_dsg + (size_t)s0 * kMaxPivot, d_dm + s0, d_dnf + s0, cnt};
-        run_task(blocks, dl, s0, 0, inner_max);
+        run_task(blocks, dl, s0, 0, inner_max, d_promote_diag);
       }
     }
-    const bool block_oriented = o.inner_mode == 0 && P.nbl > 2;
+    const bool block_oriented = imode == 0 && P.nbl > 2;
     const int imax = block_oriented ? 1 : inner_max;
     for (int t = 0; t < P.nsteps; t++) {
       const int count = P.count[t];
@@ -843,7 +857,7 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
         }
         const size_t base = (size_t)t * h + s0;
         PivotList pl{d_cols + base * kMaxPivot, d_sg + base * kMaxPivot, d_m + base, d_nf + base, cnt};
-        run_task(blocks, pl, s0, mode, imax);
+        run_task(blocks, pl, s0, mode, imax, d_promote + (size_t)t * h);
       }
     }
   };
@@ -869,7 +883,7 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
   if (direct) {
     PivotList pl{d_cols, d_sg, d_m, d_nf, P.count[0]};
     size_t k0 = prof.arm();
-    pivot(d_part, nch, m, rows_g, pl, tol, max_sweeps, 3, 0, d_W, d_rot, d_st, stream, Batch(), nullptr, nullptr, G,
+    pivot(d_part, nch, m, rows_g, pl, tol, tol, max_sweeps, 3, 0, d_W, d_rot, d_st, stream, Batch(), nullptr, nullptr, G,
           ldg);
     prof.done_kernel(JJ_K_PIVOT, k0, pl.count);
     ck(hipGetLastError(), "launch");
@@ -990,6 +1004,7 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     info->mixed_sweeps = mixed_sweeps;
     info->mixed_resolved = mixed_resolved;
+    info->inner_mode = imode;
   }
   return status;
 }
@@ -1013,9 +1028,9 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
 
 
 static int tune_block_width(int dtype, void* G, const signed char* J, int n, int ldg, hipStream_t stream,
-                            bool wide) {
+                            bool wide, bool modes) {
   const int w = dtype == JJ_C128 ? 2 : 1;
-  if (n <= 64) return 32;  // one pivot holds the whole problem for either width
+  if (n <= 64) return 32 * 2;  // one pivot holds the whole problem for either width
   const size_t gsz = (size_t)n * n * w * sizeof(double);
   double *Gc = nullptr, *lam = nullptr, *V = nullptr;
   ck(hipMalloc((void**)&Gc, gsz), "hipMalloc tune");
@@ -1025,32 +1040,40 @@ static int tune_block_width(int dtype, void* G, const signed char* J, int n, int
   ck(hipEventCreate(&e0), "event");
   ck(hipEventCreate(&e1), "event");
   // Up to n = 2048 each candidate runs a whole solve (time to solution: the
-  // widths need different sweep counts); above, two sweeps (a solve there
+  // candidates need different sweep counts); above, two sweeps (a solve there
   // takes from 0.2 s to seconds, and the measured sweep counts of the widths
-  // differ by a few percent).
+  // differ by a few percent).  The full-diagonalisation variant needs far fewer
+  // sweeps at a far higher cost per sweep, so it is a candidate only where
+  // whole solves are timed, up to n = 1024.
   const bool whole = n <= 2048;
-  int best = 32;
+  std::vector<std::pair<int, int>> cand = {{32, 0}, {16, 0}};
+  if (wide) cand.push_back({64, 0});
+  if (modes && n <= 1024) {
+    cand.push_back({32, 1});
+    cand.push_back({16, 1});
+  }
+  int best = 32 * 2;
   float best_ms = 1e30f;
-  std::vector<int> cand = {32, 16};
-  if (wide) cand.push_back(64);
-  for (int c : cand) {  // untimed: workspace growth and first launches
+  for (const auto& c : cand) {  // untimed: workspace growth and first launches
     ck(hipMemcpy2DAsync(Gc, (size_t)n * w * sizeof(double), G, (size_t)ldg * w * sizeof(double),
                         (size_t)n * w * sizeof(double), n, hipMemcpyDeviceToDevice, stream),
        "copy tune");
     jj_opts o;
     jjacobi_default_opts(&o);
     o.stream = stream;
-    o.block_width = c;
+    o.block_width = c.first;
+    o.inner_mode = c.second;
     solve_one(dtype, Gc, J, n, n, lam, V, n, 0.0, 1, o, nullptr, false);
   }
-  for (int c : cand) {
+  for (const auto& c : cand) {
     ck(hipMemcpy2DAsync(Gc, (size_t)n * w * sizeof(double), G, (size_t)ldg * w * sizeof(double),
                         (size_t)n * w * sizeof(double), n, hipMemcpyDeviceToDevice, stream),
        "copy tune");
     jj_opts o;
     jjacobi_default_opts(&o);
     o.stream = stream;
-    o.block_width = c;
+    o.block_width = c.first;
+    o.inner_mode = c.second;
     ck(hipEventRecord(e0, stream), "event");
     solve_one(dtype, Gc, J, n, n, lam, V, n, 0.0, whole ? 0 : 2, o, nullptr, whole);
     ck(hipEventRecord(e1, stream), "event");
@@ -1059,7 +1082,7 @@ static int tune_block_width(int dtype, void* G, const signed char* J, int n, int
     ck(hipEventElapsedTime(&ms, e0, e1), "event");
     if (ms < best_ms) {
       best_ms = ms;
-      best = c;
+      best = c.first * 2 + c.second;
     }
   }
   hipEventDestroy(e0);
@@ -1091,7 +1114,7 @@ static int solve_batch(int count, const int* dtype, void* const* G, const signed
       bw[i] = std::min(o.block_width, kMaxBlock);
       continue;
     }
-    bw[i] = tuned_block_width(dtype[i], G[i], J[i], n[i], ldg[i], caller);
+    bw[i] = tuned_block_width(dtype[i], G[i], J[i], n[i], ldg[i], caller) >> 1;
   }
 
   // per-problem plans; tables concatenated per dtype group
@@ -1303,7 +1326,7 @@ static int solve_batch(int count, const int* dtype, void* const* G, const signed
   for (int i = 0; i < count; i++) ptol[i] = tol > 0.0 ? tol : (double)n[i] * std::ldexp(1.0, -53);
   up(d_tol, ptol.data(), count * sizeof(double));
   const double btol = 0.0;  // unused: the pivot solver reads the per-problem value
-  const bool block_oriented = o.inner_mode == 0;
+  const bool block_oriented = o.inner_mode <= 0;
   const int pmode = block_oriented ? 2 : 0;
   const int imax = block_oriented ? 1 : (o.inner_max_sweeps > 0 ? o.inner_max_sweeps : 12);
 
@@ -1326,20 +1349,15 @@ static int solve_batch(int count, const int* dtype, void* const* G, const signed
     for (int g = 0; g < 2; g++) {
       if (grp[g].slots == 0) continue;
       PivotList pl{dg[g].cols, dg[g].sg, dg[g].m, dg[g].nfirst, grp[g].slots};
-      if (!mixed) {
+      if (!mixed)
         (g ? launch_gram_c128 : launch_gram_f64)(nullptr, 0, 0, pl, 1, rows_g[g], dg[g].part, s, bt[g], nullptr);
-      } else {  // FP64 Gram for the problems in FP64 sweeps, FP32-MFMA Gram for the others
-        Batch b64 = bt[g], b32 = bt[g];
-        b64.prec_sel = 0;
-        b32.prec_sel = 1;
-        (g ? launch_gram_c128 : launch_gram_f64)(nullptr, 0, 0, pl, 1, rows_g[g], dg[g].part, s, b64, nullptr);
-        (g ? launch_gram_c64mix : launch_gram_f32mix)(nullptr, 0, 0, pl, 1, rows_g[g], dg[g].part, s, b32);
-      }
+      else  // one launch: FP64 for the problems in FP64 sweeps, FP32 MFMA for the others
+        launch_gram_sel(g == 1, nullptr, 0, 0, pl, 1, rows_g[g], dg[g].part, s, bt[g], nullptr);
     }
     for (int g = 0; g < 2; g++) {
       if (grp[g].slots == 0) continue;
       PivotList pl{dg[g].cols, dg[g].sg, dg[g].m, dg[g].nfirst, grp[g].slots};
-      (g ? launch_pivot_c128 : launch_pivot_f64)(dg[g].part, 1, 0, rows_g[g], pl, btol, imax, pmode, 0, dg[g].W,
+      (g ? launch_pivot_c128 : launch_pivot_f64)(dg[g].part, 1, 0, rows_g[g], pl, btol, btol, imax, pmode, 0, dg[g].W,
                                                  dg[g].rot, nullptr, s, bt[g], nullptr, nullptr, nullptr, 0);
     }
     for (int g = 0; g < 2; g++) {
@@ -1517,6 +1535,7 @@ void jjacobi_default_opts(jj_opts* o) {
   std::memset(o, 0, sizeof(*o));
   o->block_width = 0;  // library choice (tuned where it matters)
   o->inner_max_sweeps = 12;
+  o->inner_mode = -1;  // library choice
   o->mixed_switch = 1e-5;
 }
 
