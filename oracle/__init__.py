@@ -53,6 +53,9 @@ def load(path=_SO):
         f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                       ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                       ctypes.c_void_p, ctypes.c_void_p]
+        f = getattr(lib, "jjo_nullspace_" + sfx)
+        f.restype = ctypes.c_int
+        f.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
         f = getattr(lib, "jjo_bp_factor_" + sfx)
         f.restype = ctypes.c_int
         f.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_void_p,
@@ -126,3 +129,20 @@ def bp_factor(H, tol=0.0, precision="double", lib=None):
                                               _ptr(piv))
     r = rank.value
     return dict(G=G[:, :r], J=J[:r], rank=r, perm=perm[:n], pivsize=piv[:n], status=st)
+
+
+def nullspace(U, precision="double", lib=None):
+    """Orthonormal basis Z (n x (n - r)) of the orthogonal complement of the
+    columns of U (n x r, orthonormal columns): the last n - r columns of the Q
+    of U's Householder QR factorization (Section 2.2, last paragraph)."""
+    lib = lib or load()
+    U = np.asarray(U)
+    n, r = U.shape
+    cplx = np.iscomplexobj(U)
+    Uf = np.asfortranarray(U, dtype=np.complex128 if cplx else np.float64)
+    Z = np.zeros((n, n - r), dtype=np.complex128 if cplx else np.float64, order="F")
+    sfx = ("l" if precision == "long" else "") + ("z" if cplx else "d")
+    st = getattr(lib, "jjo_nullspace_" + sfx)(_ptr(Uf) if n else None, n, r, max(n, 1), _ptr(Z) if n > r else None)
+    if st != 0:
+        raise ValueError("jjo_nullspace: %d" % st)
+    return Z

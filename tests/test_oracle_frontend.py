@@ -129,6 +129,81 @@ def bp_battery(factor, solve_rect):
     return fails
 
 
+def null_battery(nullspace, factor, solve_rect):
+    """Pins of the null-space completion: orthonormal columns orthogonal to U,
+    the projector identity Z Z^* + U U^* = I, and H Z = 0 for a singular H."""
+    fails = []
+    rng = np.random.default_rng(17)
+    for cplx in (False, True):
+        for n, r in ((30, 11), (9, 1), (12, 11)):
+            X = rng.standard_normal((n, r)) + (1j * rng.standard_normal((n, r)) if cplx else 0)
+            U, _ = np.linalg.qr(X)
+            Z = nullspace(U)
+            ok = Z.shape == (n, n - r)
+            tag = "n=%d r=%d cplx=%d" % (n, r, cplx)
+            if not ok:
+                fails.append("shape " + tag)
+                continue
+            if np.max(np.abs(Z.conj().T @ Z - np.eye(n - r))) > 16 * n * EPS:
+                fails.append("orthonormal " + tag)
+            if np.max(np.abs(U.conj().T @ Z)) > 16 * n * EPS:
+                fails.append("orthogonal to U " + tag)
+            if np.max(np.abs(Z @ Z.conj().T + U @ U.conj().T - np.eye(n))) > 16 * n * EPS:
+                fails.append("projector " + tag)
+    # the null space of a singular H through the front end and the rectangular solve
+    for cplx in (False, True):
+        n, rk = 11, 6
+        B = rng.integers(-3, 4, size=(n, rk)).astype(float)
+        if cplx:
+            B = B + 1j * rng.integers(-3, 4, size=(n, rk))
+        H = B @ (np.array([1, -1, 1, -1, 1, 1])[:, None] * B.conj().T)
+        f = factor(H)
+        sv = solve_rect(f["G"], f["J"])
+        Z = nullspace(sv["V"])
+        if Z.shape != (n, n - rk) or np.linalg.norm(H @ Z) > 64 * n * EPS * np.linalg.norm(H):
+            fails.append("H Z = 0 cplx=%d" % cplx)
+    return fails
+
+
+def test_nullspace_battery():
+    assert null_battery(oracle.nullspace, _factor(), _solve_rect()) == []
+    # r = 0: Q = I;  r = n: nothing to complete
+    assert np.array_equal(oracle.nullspace(np.zeros((5, 0))), np.eye(5))
+    assert oracle.nullspace(np.eye(4)).shape == (4, 0)
+
+
+NULL_MUTATIONS = {
+    "reflectors_forward_order": ("for (int k = r - 1; k >= 0; k--) {", "for (int k = 0; k < r; k++) {"),
+    "dot_without_conj_e": ("for (int i = k; i < n; i++) s += FN(bp_conj)(v[i]) * e[i];",
+                           "for (int i = k; i < n; i++) s += v[i] * e[i];"),
+    "reflector_factor_one": ("const ST f = s * ((RT)2 / beta[k]);", "const ST f = s * ((RT)1 / beta[k]);"),
+    "identity_rows_from_top": ("for (int c = 0; c < n - r; c++) E[(size_t)c * n + r + c] = 1;",
+                               "for (int c = 0; c < n - r; c++) E[(size_t)c * n + c] = 1;"),
+    "last_column_not_updated": ("for (int j = k; j < r; j++) {", "for (int j = k; j < r - 1; j++) {"),
+}
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(NULL_MUTATIONS))
+def test_nullspace_mutation_is_caught(name, tmp_path):
+    old, new = NULL_MUTATIONS[name]
+    src = os.path.dirname(oracle.__file__)
+    for f in ("jj_oracle.c", "jj_oracle_body.inc", "jj_bp_body.inc"):
+        shutil.copy(os.path.join(src, f), tmp_path / f)
+    body = (tmp_path / "jj_bp_body.inc").read_text()
+    assert body.count(old) >= 1, "mutation target not found in the source"
+    (tmp_path / "jj_bp_body.inc").write_text(body.replace(old, new))
+    so = str(tmp_path / "libmut.so")
+    oracle.build(out=so, src_dir=str(tmp_path))
+    lib = oracle.load(so)
+    with np.errstate(all="ignore"):
+        try:
+            fails = null_battery(lambda U: oracle.nullspace(U, lib=lib), _factor(lib), _solve_rect(lib))
+        except (np.linalg.LinAlgError, ValueError):
+            fails = ["exception"]
+    assert fails, "planted mistake %r was not caught by any pin" % name
+
+
 def _factor(lib=None, precision="double"):
     return lambda H: oracle.bp_factor(H, precision=precision, lib=lib)
 
