@@ -203,8 +203,10 @@ int jjacobi_factor(int dtype, const void* H, int n, int ldh, void* G, int ldg, s
  * tolerance) followed by jjacobi_solve_rect on the n x r factor.  H (device,
  * n x n, ldh, lower triangle read) is destroyed: G is formed in its storage.
  * lambda (n doubles): the r nonzero eigenvalues descending, then n - r zeros;
- * V (n x n, ldv >= n): their unit eigenvectors, then n - r zero columns (the
- * null space of a singular H is not formed).  info->rank receives r.  tol and
+ * V (n x n, ldv >= n): their unit eigenvectors, then an orthonormal basis of
+ * the null space of a singular H (the last n - r columns of Q in the
+ * Householder QR of the first r columns, Section 2.2).  info->rank receives
+ * r.  tol and
  * max_sweeps as for the solve.  Status codes as jjacobi_solve_ex (argument k of
  * this signature for -k). */
 int jjacobi_eigh(int dtype, void* H, int n, int ldh, double* lambda, void* V, int ldv, double tol,

@@ -218,8 +218,8 @@ def factor(H, tol=0.0, **opts):
 def eigh(H, tol=0.0, max_sweeps=0, **opts):
     """Eigenpairs of a Hermitian CUDA tensor H (n x n) through the front end and
     the one-sided J-Jacobi solve.  Returns (lam (n,), V (n, n), info); info['rank']
-    is the rank found (the last n - rank eigenvalues are zero, their vectors are
-    zero columns)."""
+    is the rank found (the last n - rank eigenvalues are zero, their vectors an
+    orthonormal basis of H's null space)."""
     import torch
     n = H.shape[0]
     cplx = H.dtype == torch.complex128

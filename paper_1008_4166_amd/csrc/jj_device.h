@@ -258,6 +258,13 @@ void launch_bp_update(double* A, int n, int cplx, const double* pcol, BPState* s
 // Pivot choice, symmetric interchanges, column(s) of M; pcol receives the unscaled pivot columns.
 void launch_bp_select(double* A, int n, int cplx, double tol, double* pcol, BPState* st, const BPPartial* part,
                       int* perm, int* piv, double* dblk, hipStream_t stream);
+// Null space of a singular H: Householder QR of A (n x r, ld n; overwritten;
+// reflectors to Vh, n x r, and beta, r), then E (n x (n - r), ld lde) = the
+// last n - r columns of Q.  r >= 1, r < n.
+void launch_nullspace(int cplx, double* A, int n, int r, double* Vh, double* beta, double* E, int lde,
+                      hipStream_t stream);
+// E (n x (n - r), ld lde) = rows r.. of the n x n identity (r = 0: E = I).
+void launch_identity_tail(int cplx, double* E, int n, int lde, int r, hipStream_t stream);
 // G = P^T M Q |Lambda|^{1/2} (first st->rank columns; the others zeroed) and J.
 void launch_bp_build_g(const double* A, int n, int cplx, const BPState* st, const int* perm, const int* piv,
                        const double* dblk, double* G, int ldg, signed char* J, hipStream_t stream);

@@ -399,6 +399,113 @@ __global__ void k_bp_init(BPState* st, int* perm, int n) {
   }
 }
 
+// ---- null space of a singular H (Section 2.2, last paragraph): Householder QR
+// of U~ (n x r) and the last n - r columns of its Q ----
+
+// fixed-order sum over the workgroup (kBpThreads values in LDS)
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  const int tid = threadIdx.x;
+  red[tid] = v;
+  __syncthreads();
+  for (int h = kBpThreads / 2; h > 0; h >>= 1) {
+    if (tid < h) red[tid] += red[tid + h];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Reflector of x = A[k:, k]: v = x - alpha e_1, alpha = -e^{i arg x_k} ||x||
+// (sgn 0 = +1), beta = ||v||^2; v (zero above row k) to Vh[:, k].  One workgroup.
+__global__ __launch_bounds__(kBpThreads) void k_hh_reflector(const double* __restrict__ A, int n, int lda, int w,
+                                                             int k, double* __restrict__ Vh, double* __restrict__ beta) {
+  __shared__ double red[kBpThreads];
+  const int tid = threadIdx.x;
+  const double* x = A + (size_t)k * lda * w;
+  double* v = Vh + (size_t)k * n * w;
+  double s2 = 0.0;
+  for (int i = k + tid; i < n; i += kBpThreads) {
+    const double xr = x[(size_t)i * w], xi = w == 2 ? x[(size_t)i * w + 1] : 0.0;
+    s2 += xr * xr + xi * xi;
+  }
+  const double nx = sqrt(block_sum(s2, red));
+  const double x0r = x[(size_t)k * w], x0i = w == 2 ? x[(size_t)k * w + 1] : 0.0;
+  const double a0 = w == 2 ? hypot(x0r, x0i) : fabs(x0r);
+  const double phr = a0 > 0.0 ? x0r / a0 : 1.0, phi = a0 > 0.0 ? x0i / a0 : 0.0;
+  double b2 = 0.0;
+  for (int i = tid; i < n; i += kBpThreads) {
+    double vr = 0.0, vi = 0.0;
+    if (i > k) {
+      vr = x[(size_t)i * w];
+      vi = w == 2 ? x[(size_t)i * w + 1] : 0.0;
+    } else if (i == k) {
+      vr = x0r + phr * nx;
+      vi = x0i + phi * nx;
+    }
+    v[(size_t)i * w] = vr;
+    if (w == 2) v[(size_t)i * w + 1] = vi;
+    b2 += vr * vr + vi * vi;
+  }
+  const double b = block_sum(b2, red);
+  if (tid == 0) beta[k] = b;
+}
+
+// M[:, j] -= (2 / beta_k) v_k (v_k^* M[:, j]) over rows k..n-1, for the ncols
+// columns starting at col0; one workgroup per column.
+__global__ __launch_bounds__(kBpThreads) void k_hh_apply(double* __restrict__ M, int n, int ldm, int w, int col0,
+                                                         const double* __restrict__ Vh, const double* __restrict__ beta,
+                                                         int k) {
+  __shared__ double red[kBpThreads];
+  const int tid = threadIdx.x;
+  const double b = beta[k];
+  if (!(b > 0.0)) return;
+  double* m = M + (size_t)(col0 + blockIdx.x) * ldm * w;
+  const double* v = Vh + (size_t)k * n * w;
+  double sr = 0.0, si = 0.0;
+  for (int i = k + tid; i < n; i += kBpThreads) {
+    const double vr = v[(size_t)i * w], vi = w == 2 ? v[(size_t)i * w + 1] : 0.0;
+    const double mr = m[(size_t)i * w], mi = w == 2 ? m[(size_t)i * w + 1] : 0.0;
+    sr += vr * mr + vi * mi;  // conj(v) m
+    si += vr * mi - vi * mr;
+  }
+  sr = block_sum(sr, red);
+  if (w == 2) si = block_sum(si, red);
+  const double fr = sr * (2.0 / b), fi = si * (2.0 / b);
+  for (int i = k + tid; i < n; i += kBpThreads) {
+    const double vr = v[(size_t)i * w], vi = w == 2 ? v[(size_t)i * w + 1] : 0.0;
+    m[(size_t)i * w] -= vr * fr - vi * fi;
+    if (w == 2) m[(size_t)i * w + 1] -= vr * fi + vi * fr;
+  }
+}
+
+// E (n x ncols, ld lde) = rows r.. of the identity: E[i, c] = (i == r + c)
+__global__ void k_identity_tail(double* __restrict__ E, int n, int lde, int w, int r) {
+  const int c = blockIdx.x;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    E[((size_t)c * lde + i) * w] = i == r + c ? 1.0 : 0.0;
+    if (w == 2) E[((size_t)c * lde + i) * w + 1] = 0.0;
+  }
+}
+
+void launch_identity_tail(int cplx, double* E, int n, int lde, int r, hipStream_t stream) {
+  if (n > r) launch(k_identity_tail, dim3(n - r), dim3(256), 0, stream, E, n, lde, cplx ? 2 : 1, r);
+}
+
+void launch_nullspace(int cplx, double* A, int n, int r, double* Vh, double* beta, double* E, int lde,
+                      hipStream_t stream) {
+  const int w = cplx ? 2 : 1;
+  for (int k = 0; k < r; k++) {
+    launch(k_hh_reflector, dim3(1), dim3(kBpThreads), 0, stream, (const double*)A, n, n, w, k, Vh, beta);
+    launch(k_hh_apply, dim3(r - k), dim3(kBpThreads), 0, stream, A, n, n, w, k, (const double*)Vh,
+           (const double*)beta, k);
+  }
+  launch(k_identity_tail, dim3(n - r), dim3(256), 0, stream, E, n, lde, w, r);
+  for (int k = r - 1; k >= 0; k--)
+    launch(k_hh_apply, dim3(n - r), dim3(kBpThreads), 0, stream, E, n, lde, w, 0, (const double*)Vh,
+           (const double*)beta, k);
+}
+
 void launch_bp_init(BPState* st, int* perm, int n, hipStream_t stream) {
   launch(k_bp_init, dim3((n + 255) / 256), dim3(256), 0, stream, st, perm, n);
 }

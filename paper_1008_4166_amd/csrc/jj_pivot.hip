@@ -425,27 +425,11 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
     tol = tol64;
   }
   const signed char* sg = s_sg;  // signs of the pivot's columns, in LDS
+  // the instances that serve the direct mode (mode 3): single solves, the real
+  // lane-read Cholesky form and the complex kernel
+  constexpr bool kDirect = !DENSE && (CPLX || CHOL == 0);
 
-  if (mode == 3) {
-    // ---- direct (one pivot holding all n <= kMaxPivot columns of G): the
-    // non-blocked one-sided J-Jacobi on G itself (Algorithm 3.2), G's rows in
-    // place of R's; no Gram block, no Cholesky ----
-    const T* Gc = reinterpret_cast<const T*>(Gm);
-    for (int e = tid; e < kMaxPivot * kMaxPivot; e += NT) {
-      const int r = e & 63, c = e >> 6;
-      if (c < m) {
-        R[c * LDR + r] = r < n ? Gc[(size_t)cols[p * kMaxPivot + c] * ldgm + r] : zero_of(T());
-        T one = zero_of(T());
-        if constexpr (CPLX) one.x = (r == c) ? 1.0 : 0.0; else one = (r == c) ? 1.0 : 0.0;
-        W[c * LDR + r] = one;
-      }
-    }
-    if (tid == 0) {
-      s_bad = 0;
-      s_cnt = 0;
-    }
-    __syncthreads();
-  } else {
+  {
   // ---- 1. A_P = sum of the chunk partials (upper 16x16 tiles), Hermitian fill ----
   // Thread u of each 256-element tile takes element (u / 16, u % 16) of it; the
   // chunk loads of EB tiles are issued together, then summed in chunk order.
@@ -519,7 +503,7 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
   for (int w = 1; w < NT / 64; w++) off = fmax(off, redv[w]);
   if constexpr (CPLX) off = sqrt_nr(off);
   if (tid == 0) atomic_max_nonneg(&st->max_off_bits, isfinite(off) ? off : 1.0e300);
-  if (s_bad || off <= tol) {
+  if (s_bad || (off <= tol && !(kDirect && mode == 3))) {
     if (tid == 0) {
       rotflag[bslot] = 0;
       if (s_bad) {
@@ -607,14 +591,29 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
     }
   }
 
-  }  // mode != 3
+  }  // phases 1-3
+
+  // ---- direct mode (one pivot holding all n <= kMaxPivot columns of G): the
+  // non-blocked one-sided J-Jacobi on G itself (Algorithm 3.2), G's rows in
+  // place of R's.  The Gram block and its Cholesky factor above serve only to
+  // test that G has full column rank to working precision, as in every blocked
+  // step (a failed factorisation is a breakdown). ----
+  if (kDirect && mode == 3) {
+    __syncthreads();  // the factor in R is no longer read
+    const T* Gc = reinterpret_cast<const T*>(Gm);
+    for (int e = tid; e < kMaxPivot * kMaxPivot; e += NT) {
+      const int r = e & 63, c = e >> 6;
+      if (c < m) R[c * LDR + r] = r < n ? Gc[(size_t)cols[p * kMaxPivot + c] * ldgm + r] : zero_of(T());
+    }
+    __syncthreads();
+  }
 
   // ---- 4. inner sweeps ----
   // half 0 (threads 0..HT-1) holds columns of R, half 1 columns of W_P in the
   // split cross pass; elsewhere half 0 works on both and half 1 waits
   const int half = tid / HT, slot = (tid % HT) / LPS, sub = tid % LPS;
   const int L = max(n1, n2);
-  const bool full = mode == 0 || mode == 3;  // within-block pairs too, inner sweeps up to inner_max
+  const bool full = mode == 0 || (kDirect && mode == 3);  // within-block pairs too, inner sweeps up to inner_max
   const int nsweeps = full ? inner_max : 1;
   int total = 0, sweeps_run = 0, last_cnt = 0;
   for (int it = 0; it < nsweeps; it++) {
@@ -657,7 +656,7 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
               Rr[i] = lin2(cs, f, -sigma * sn, g);
               Rs[i] = lin2(sn, f, cs, g);
             }
-            if (mode != 3) {  // the direct mode keeps no W_P
+            if (!(kDirect && mode == 3)) {  // the direct mode keeps no W_P
               T* Wr = W + (base + r) * LDR;
               T* Ws = W + (base + s) * LDR;
               for (int i = sub; i < m; i += LPS) {
@@ -944,7 +943,7 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
     return;
   }
 
-  if (mode == 3) {
+  if (kDirect && mode == 3) {
     // G~ = G W: the rotated columns go back to G; converged iff the last inner
     // sweep applied no rotation (counted in pivots_rotated otherwise)
     T* Gc = reinterpret_cast<T*>(Gm);

@@ -875,17 +875,14 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
   };
   SweepGraphs graphs;
   // At most kMaxPivot columns and rows (two blocks: a single pivot holding the
-  // whole matrix): the non-blocked process on G itself in one launch
+  // whole matrix): the non-blocked process on G itself in one pivot launch
   // (Algorithm 3.2, inner sweeps until one applies no rotation, capped by
-  // max_sweeps): no Gram block, no Cholesky, no update.  sweeps counts its
-  // sweeps.
+  // max_sweeps), no update.  The Gram block and its Cholesky factor serve only
+  // the full-rank test of the blocked steps.  sweeps counts the inner sweeps.
   const bool direct = P.nbl == 2 && P.nsteps == 1 && m == n && n <= kMaxPivot && !mixed && o.diag_pass == 0;
   if (direct) {
     PivotList pl{d_cols, d_sg, d_m, d_nf, P.count[0]};
-    size_t k0 = prof.arm();
-    pivot(d_part, nch, m, rows_g, pl, tol, tol, max_sweeps, 3, 0, d_W, d_rot, d_st, stream, Batch(), nullptr, nullptr, G,
-          ldg);
-    prof.done_kernel(JJ_K_PIVOT, k0, pl.count);
+    gram_pivot(false, pl, d_part, d_W, d_rot, nullptr, 3, max_sweeps);
     ck(hipGetLastError(), "launch");
     ck(hipMemcpyAsync(&hst, d_st, sizeof(hst), hipMemcpyDeviceToHost, stream), "D2H");
     ck(hipStreamSynchronize(stream), "sync");
@@ -1681,22 +1678,41 @@ int jjacobi_eigh(int dtype, void* H, int n, int ldh, double* lambda, void* V, in
       StreamJoin join((hipStream_t)o.stream, stream);
       // G overwrites H (H is copied into the workspace first)
       st = bp_factor_dev(dtype, H, n, ldh, (double*)H, ldh, J.data(), &r, 0.0, stream);
-      if (st == JJ_OK && r < n) {
-        // the zero eigenvalue (multiplicity n - r) at the end; its vectors are not formed
+      if (st == JJ_OK && r < n)  // the zero eigenvalue (multiplicity n - r) at the end
         ck(hipMemsetAsync(lambda + r, 0, (size_t)(n - r) * sizeof(double), stream), "memset");
-        ck(hipMemset2DAsync((double*)V + (size_t)r * ldv * w, (size_t)ldv * w * sizeof(double), 0,
-                            (size_t)n * w * sizeof(double), n - r, stream),
-           "memset");
-      }
     }
     if (st != JJ_OK) {
       if (info) info->status = st;
       return st;
     }
     if (info) info->rank = r;
-    if (r == 0) return JJ_OK;
+    if (r == 0) {
+      // H = 0: every vector is an eigenvector; V = I
+      hipStream_t stream = lib_stream();
+      StreamJoin join((hipStream_t)o.stream, stream);
+      launch_identity_tail(dtype == JJ_C128, (double*)V, n, ldv, 0, stream);
+      ck(hipGetLastError(), "launch");
+      ck(hipStreamSynchronize(stream), "sync");
+      return JJ_OK;
+    }
     st = solve_one(dtype, H, J.data(), r, ldh, lambda, V, ldv, tol, max_sweeps, o, info, true, false, n);
     if (info) info->rank = r;
+    if (r < n && st <= JJ_NOT_CONVERGED) {
+      // the eigenvectors of the zero eigenvalue: the complement of the r
+      // eigenvectors, from the Householder QR of V[:, 0:r] (Section 2.2)
+      hipStream_t stream = lib_stream();
+      StreamJoin join((hipStream_t)o.stream, stream);
+      Carver c{arena_get((size_t)2 * n * r * w * sizeof(double) + (size_t)r * sizeof(double) + 4096)};
+      double* A = c.take<double>((size_t)n * r * w);
+      double* Vh = c.take<double>((size_t)n * r * w);
+      double* beta = c.take<double>(r);
+      ck(hipMemcpy2DAsync(A, (size_t)n * w * sizeof(double), V, (size_t)ldv * w * sizeof(double),
+                          (size_t)n * w * sizeof(double), r, hipMemcpyDeviceToDevice, stream),
+         "copy U");
+      launch_nullspace(dtype == JJ_C128, A, n, r, Vh, beta, (double*)V + (size_t)r * ldv * w, ldv, stream);
+      ck(hipGetLastError(), "launch");
+      ck(hipStreamSynchronize(stream), "sync");
+    }
     return st;
   } catch (const HipFail&) {
     if (info) info->status = JJ_HIP_ERROR;

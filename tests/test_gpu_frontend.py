@@ -99,9 +99,17 @@ def test_singular_H(cplx):
     torch.cuda.synchronize()
     lg, V = lg.cpu().numpy(), V.cpu().numpy()
     assert info["status"] == 0 and info["rank"] == rk
-    ro = oracle.solve(r["G"], r["J"], vectors=False)
+    ro = oracle.solve(r["G"], r["J"])
     assert rel_err(lg[:rk], ro["lam"]) <= 1e-12
-    assert np.all(lg[rk:] == 0) and np.all(V[:, rk:] == 0)
+    assert np.all(lg[rk:] == 0)
+    # the null space (Householder QR of U~): a basis is not unique, its
+    # projector is; against the oracle's completion of the oracle's U~
+    Z = V[:, rk:]
+    assert np.max(np.abs(Z.conj().T @ Z - np.eye(n - rk))) <= 16 * n * EPS
+    assert np.max(np.abs(V[:, :rk].conj().T @ Z)) <= 16 * n * EPS
+    assert np.linalg.norm(H @ Z) <= 64 * n * EPS * np.linalg.norm(H)
+    Zo = oracle.nullspace(ro["V"])
+    assert np.max(np.abs(Z @ Z.conj().T - Zo @ Zo.conj().T)) <= 1e-12
     ev = np.linalg.eigvalsh(H)
     nz = np.sort(ev[np.argsort(-np.abs(ev))[:rk]])[::-1]
     assert rel_err(lg[:rk], nz) <= 1e-10
@@ -132,6 +140,15 @@ def test_rect_solve_against_oracle(cplx, m, n):
     HV = G @ (J.astype(float)[:, None] * (G.conj().T @ V))
     assert np.linalg.norm(HV - V * lg[None, :]) / np.linalg.norm(lg) <= 1e-10
     assert np.max(np.abs(V.conj().T @ V - np.eye(n))) <= 16 * m * EPS
+
+
+def test_eigh_zero_matrix():
+    # H = 0: rank 0, every eigenvalue zero, V = I
+    jj = _jj()
+    lg, V, info = jj.eigh(torch.zeros((6, 6), dtype=torch.complex128, device="cuda"))
+    torch.cuda.synchronize()
+    assert info["status"] == 0 and info["rank"] == 0
+    assert np.all(lg.cpu().numpy() == 0) and np.array_equal(V.cpu().numpy(), np.eye(6))
 
 
 def test_factor_status_paths():
