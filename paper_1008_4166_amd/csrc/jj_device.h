@@ -41,6 +41,7 @@ struct PivotList {
   const int* m;
   const int* nfirst;
   int count;
+  bool full = false;  // every pivot of the list has kMaxPivot columns (host-side knowledge)
 };
 
 // Optional batch descriptor.  A launch over S slots serves many independent

@@ -721,6 +721,15 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
           use_mix ? promote : nullptr, nullptr, G, ldg);
     prof.done_kernel(JJ_K_PIVOT, k0, pl.count);
   };
+  // steps whose pivots all have kMaxPivot columns: their update launches the
+  // instance without per-column bounds
+  std::vector<char> full_step(P.nsteps, 0);
+  if (!P.m.empty())
+    for (int t = 0; t < P.nsteps; t++) {
+      bool f = P.count[t] > 0;
+      for (int k = 0; k < P.count[t]; k++) f = f && P.m[(size_t)t * h + k] == kMaxPivot;
+      full_step[t] = f;
+    }
   auto enqueue_sweep = [&](bool use_mix, bool diag) {
     size_t k0 = prof.mark();
     launch_reset_stats(d_st, stream);
@@ -770,6 +779,7 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
     for (int t = 0; t < P.nsteps && !three; t++) {
       PivotList pl{d_cols + (size_t)t * h * kMaxPivot, d_sg + (size_t)t * h * kMaxPivot, d_m + (size_t)t * h,
                    d_nf + (size_t)t * h, P.count[t]};
+      pl.full = full_step[t];
       if (pl.count == 0) continue;
       // Block-oriented variant (Section 5.3): the first step of a sweep makes one
       // full pass over its pivots (covering every diagonal block), the other
