@@ -67,14 +67,23 @@ def algorithmic_work(prof, n, cplx):
     return out
 
 
+def _code_tokens(text):
+    """Source text without C/C++ comments, whitespace runs collapsed: what the
+    compiler sees, so that a comment-only edit keeps the recorded counters."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def sources_sha256():
     import glob
     import hashlib
     h = hashlib.sha256()
     for f in sorted(glob.glob(os.path.join(ROOT, "paper_1008_4166_amd", "csrc", "*"))):
         h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f, encoding="utf-8", errors="replace") as fh:
+            h.update(_code_tokens(fh.read()).encode())
     return h.hexdigest()
 
 

@@ -175,9 +175,10 @@ void launch_fill_int(int* p, int count, int v, hipStream_t stream);
 // mode: 0 full inner sweeps (inner_max), 1 off-diagonal pass only, 2 (batched
 // block-oriented) full pass at step 0 of the problem's sweep, else off-diagonal,
 // 3 direct: a single pivot holding every column of a G of n <= kMaxPivot rows is
-// solved on G itself (no Gram block, no Cholesky; part is not read) with up to
-// inner_max inner sweeps, and the rotated columns are written back to G (G, ldg;
-// rotflag 0, pivots_rotated counts the pivot if its last inner sweep rotated).
+// solved on G itself with up to inner_max inner sweeps (its Gram block and
+// Cholesky factor only test full column rank: a failed factorisation is a
+// breakdown), and the rotated columns are written back to G (G, ldg; rotflag 0,
+// pivots_rotated counts the pivot if its last inner sweep rotated).
 // Only the first ceil(n / rows_per_chunk) partials of a pivot are summed.
 // refine (nullable, single problems in mixed sweeps): per-pair flags kept
 // across sweeps; a pivot that fails softly sets its flag (and is left for this

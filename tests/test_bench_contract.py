@@ -72,6 +72,8 @@ def test_traffic_reported_only_for_the_recorded_sources(tmp_path, monkeypatch):
     (tmp_path / "profiles" / "traffic_n4096_f64_solve.md").write_text(summary % sha)
     assert b.pmc_traffic("update") == pytest.approx((100.0 * 2.0 + 300.0) * 1024.0)
     assert b.pmc_traffic("gram") is None  # no counters for that kernel
+    (csrc / "k.hip").write_text("kernel  source // a comment\n/* and\nanother */\n")
+    assert b.pmc_traffic("update") is not None  # comments and spacing do not count
     (csrc / "k.hip").write_text("kernel source, changed\n")
     assert b.pmc_traffic("update") is None  # counters taken for other sources
 
