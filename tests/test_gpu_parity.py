@@ -152,6 +152,29 @@ def test_status_paths():
         jj.solve(torch.from_numpy(np.ascontiguousarray(G)).cuda(), Jb)
 
 
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("n", [40, 200])
+def test_rank_deficient_G_is_a_breakdown(cplx, n):
+    # Two equal columns of the same sign: G has rank n - 1 (the method needs
+    # full column rank, Section 2).  Both columns fall in the first block after
+    # sign ordering, so the first pivot holding them (n = 200: a blocked step;
+    # n = 40: the full-rank test of the direct path) cannot factor its Gram
+    # block.  They are the unit vector e_0, so that the Gram entries are 1 and
+    # the second Cholesky pivot is exactly 1 - 1 = 0, whatever the rounding of
+    # a square root.  The oracle reports status 2 for the same input (its first
+    # rotation zeroes one of the two columns).
+    G, J, _ = jjgen.make(n, cplx, n // 2, 1e-6, 1.0, seed=77)
+    G = G.copy()
+    G[:, 0] = 0.0
+    G[0, 0] = 1.0
+    G[:, 1] = G[:, 0]
+    J = J.copy()
+    J[0] = J[1] = 1
+    assert oracle.solve(G, J, vectors=False)["status"] == 2
+    lg, V, info = gpu_solve(G, J)
+    assert info["status"] == 2, info
+
+
 def test_deterministic():
     G, J, _ = jjgen.make(300, True, 120, 1e-6, 1.0, seed=1234)
     a, Va, _ = gpu_solve(G, J)
