@@ -425,6 +425,10 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
     tol = tol64;
   }
   const signed char* sg = s_sg;  // signs of the pivot's columns, in LDS
+  // the instance whose direct mode takes the within-block pairs by XOR passes
+  // in registers (real, lane-read Cholesky form; the other instances keep their
+  // register allocation)
+  constexpr bool kLevels = !DENSE && !CPLX && CHOL == 0;
   // the instances that serve the direct mode (mode 3): single solves, the real
   // lane-read Cholesky form and the complex kernel
   constexpr bool kDirect = !DENSE && (CPLX || CHOL == 0);
@@ -619,8 +623,138 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
   for (int it = 0; it < nsweeps; it++) {
     int cnt = 0;
     sweeps_run++;
-    // (a) within-block pairs, circle round-robin on each block, data in LDS
-    if (full) {
+    // One XOR pass over groups of Lv slots (Lv a power of two, Lv <= L): group
+    // g pairs columns 2 Lv g .. 2 Lv g + Lv - 1 with the next Lv columns, every
+    // pair once, in Lv rounds; Lv = L is the cross pass of the two blocks.
+    auto xor_level = [&](const int Lv) {
+      __syncthreads();  // the columns written back by the previous pass are in place
+      T* M = half == 0 ? R : W;
+      // group of Lv slots: first-block columns ca, second-block columns from cb on
+      const int local = slot & (Lv - 1), base = 2 * Lv * (slot / Lv);
+      const int ca = base + local, cb = base + Lv + local;
+      T a[RPL], b[RPL];
+#pragma unroll
+      for (int i = 0; i < RPL; i++) {
+        const int row = sub + LPS * i;
+        const bool ok = row < m && slot < L;
+        a[i] = ok ? M[ca * LDR + row] : zero_of(T());
+        b[i] = ok ? M[cb * LDR + row] : zero_of(T());
+      }
+      __syncthreads();
+      // LDS exchange buffers (aliasing R and W_P): per half two parities of 32 slots x 64 rows
+      T* ringh = lds + half * (4 * 32 * kMaxPivot / 2);
+      const double sr = slot < L ? (double)sg[ca] : 0.0;
+      double ss = slot < L ? (double)sg[cb] : 0.0;  // sign of the held second-block column (half 0)
+      for (int q = 0; q <= Lv; q++) {
+        if (half == 0 && q < Lv && slot < L) {
+          double arr = 0.0, ass = 0.0, are = 0.0, aim = 0.0;
+#pragma unroll
+          for (int i = 0; i < RPL; i++) {
+            arr += abs2(a[i]);
+            ass += abs2(b[i]);
+            cdot(a[i], b[i], are, aim);
+          }
+          arr = slot_sum<LPS>(arr);
+          ass = slot_sum<LPS>(ass);
+          are = slot_sum<LPS>(are);
+          if (CPLX) aim = slot_sum<LPS>(aim);
+          const double sigma = sr * ss;
+          double cs, sn, pr, pi;
+          const int rc = pair_rotation(arr, ass, are, aim, CPLX, sigma, tol, &cs, &sn, &pr, &pi);
+          if (sub == 0) {
+            prm[q & 1][slot][0] = cs;
+            prm[q & 1][slot][1] = sn;
+            prm[q & 1][slot][2] = -sigma * sn;
+            prm[q & 1][slot][3] = pr;
+            prm[q & 1][slot][4] = pi;
+            prc[q & 1][slot] = rc > 0;
+          }
+          if (rc > 0) {
+#pragma unroll
+            for (int i = 0; i < RPL; i++) {
+              const T f = phase_mul(pr, pi, a[i]), g = b[i];
+              a[i] = lin2(cs, f, -sigma * sn, g);
+              b[i] = lin2(sn, f, cs, g);
+            }
+            cnt += (sub == 0);
+          } else if (rc < 0 && sub == 0) {
+            atomicOr(&s_bad, 1);
+          }
+        } else if (half == 1 && q >= 1 && slot < L && prc[(q - 1) & 1][slot]) {
+          const double* pp = prm[(q - 1) & 1][slot];
+          const double cs = pp[0], sn = pp[1], msn = pp[2], pr = pp[3], pi = pp[4];
+#pragma unroll
+          for (int i = 0; i < RPL; i++) {
+            const T u = phase_mul(pr, pi, a[i]), w = b[i];
+            a[i] = lin2(cs, u, msn, w);
+            b[i] = lin2(sn, u, cs, w);
+          }
+        }
+        // move of the held column: half 0 into round q + 1, half 1 into round q
+        const int mq = half == 0 ? q + 1 : q;
+        const int bit = (mq >= 1 && mq < Lv) ? __builtin_ctz(mq) : -1;
+        const int lx = bit >= 0 ? (LPS << bit) : 0;
+        if (lx == 8) {
+          if (half == 0) ss = xor8_of(ss);
+#pragma unroll
+          for (int i = 0; i < RPL; i++) b[i] = xor8_of(b[i]);
+        } else if (lx > 0 && lx < 64) {
+          const int addr = ((tid & 63) ^ lx) << 2;
+          if (half == 0) ss = bperm_of(ss, addr);
+#pragma unroll
+          for (int i = 0; i < RPL; i++) b[i] = bperm_of(b[i], addr);
+        }
+        double2* ring = reinterpret_cast<double2*>(ringh + (q & 1) * (32 * kMaxPivot));
+        if (lx >= 64) {
+          if (half == 0 && sub == 0) ring_sg[q & 1][slot] = (int)ss;
+          if constexpr (CPLX) {
+#pragma unroll
+            for (int j = 0; j < RPL; j++) ring[(j * 32 + slot) * LPS + sub] = b[j];
+          } else {
+#pragma unroll
+            for (int j = 0; j < RPL / 2; j++) ring[(j * 32 + slot) * LPS + sub] = double2{b[2 * j], b[2 * j + 1]};
+          }
+        }
+        __syncthreads();
+        if (lx >= 64) {
+          const int from = slot ^ (1 << bit);
+          if (half == 0) ss = (double)ring_sg[q & 1][from];
+          if constexpr (CPLX) {
+#pragma unroll
+            for (int j = 0; j < RPL; j++) b[j] = ring[(j * 32 + from) * LPS + sub];
+          } else {
+#pragma unroll
+            for (int j = 0; j < RPL / 2; j++) {
+              const double2 v = ring[(j * 32 + from) * LPS + sub];
+              b[2 * j] = v.x;
+              b[2 * j + 1] = v.y;
+            }
+          }
+        }
+      }
+      __syncthreads();
+      // write the columns back: slot k holds second-block column k ^ gray(Lv - 1) = k ^ (Lv / 2)
+      const int sfin = base + Lv + (local ^ (Lv >> 1));
+      if (slot < L) {
+#pragma unroll
+        for (int i = 0; i < RPL; i++) {
+          const int row = sub + LPS * i;
+          if (row < m) {
+            M[ca * LDR + row] = a[i];
+            M[sfin * LDR + row] = b[i];
+          }
+        }
+      }
+    };
+    // (a) within-block pairs.  The direct mode with two equal power-of-two
+    // blocks (real): XOR passes over groups of L/2, L/4, ..., 1 slots, the
+    // pairs inside each half, quarter, ... of both blocks, all in registers
+    // (L - 1 rounds).  Otherwise circle round-robin on each block, data in LDS
+    // (the order that the blocked steps keep: at n = 4096 the XOR order took
+    // 40 sweeps instead of 38).
+    if (full && kLevels && mode == 3 && L >= 2 && n1 == n2 && (L & (L - 1)) == 0) {
+      for (int Lv = L >> 1; Lv >= 1; Lv >>= 1) xor_level(Lv);
+    } else if (full) {
       const int blk = slot >> 4, hs = slot & 15;  // slots 0-15: block 1, 16-31: block 2
       const int nb = blk == 0 ? n1 : n2, base = blk == 0 ? 0 : n1;
       const int nbp = nb + (nb & 1);
@@ -687,117 +821,121 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
     // shapes use the ring: slot k meets column (k + q) mod L, all columns
     // moving one slot down per round through LDS, done by half 0 alone.
     if (L > 0 && n2 > 0 && n1 == n2 && (L & (L - 1)) == 0) {
-      T* M = half == 0 ? R : W;
-      T a[RPL], b[RPL];
-#pragma unroll
-      for (int i = 0; i < RPL; i++) {
-        const int row = sub + LPS * i;
-        const bool ok = row < m && slot < L;
-        a[i] = ok ? M[slot * LDR + row] : zero_of(T());
-        b[i] = ok ? M[(n1 + slot) * LDR + row] : zero_of(T());
-      }
-      __syncthreads();
-      // LDS exchange buffers (aliasing R and W_P): per half two parities of 32 slots x 64 rows
-      T* ringh = lds + half * (4 * 32 * kMaxPivot / 2);
-      const double sr = slot < L ? (double)sg[slot] : 0.0;
-      double ss = slot < L ? (double)sg[n1 + slot] : 0.0;  // sign of the held second-block column (half 0)
-      for (int q = 0; q <= L; q++) {
-        if (half == 0 && q < L && slot < L) {
-          double arr = 0.0, ass = 0.0, are = 0.0, aim = 0.0;
-#pragma unroll
-          for (int i = 0; i < RPL; i++) {
-            arr += abs2(a[i]);
-            ass += abs2(b[i]);
-            cdot(a[i], b[i], are, aim);
-          }
-          arr = slot_sum<LPS>(arr);
-          ass = slot_sum<LPS>(ass);
-          are = slot_sum<LPS>(are);
-          if (CPLX) aim = slot_sum<LPS>(aim);
-          const double sigma = sr * ss;
-          double cs, sn, pr, pi;
-          const int rc = pair_rotation(arr, ass, are, aim, CPLX, sigma, tol, &cs, &sn, &pr, &pi);
-          if (sub == 0) {
-            prm[q & 1][slot][0] = cs;
-            prm[q & 1][slot][1] = sn;
-            prm[q & 1][slot][2] = -sigma * sn;
-            prm[q & 1][slot][3] = pr;
-            prm[q & 1][slot][4] = pi;
-            prc[q & 1][slot] = rc > 0;
-          }
-          if (rc > 0) {
-#pragma unroll
+      if constexpr (kLevels) {
+        xor_level(L);
+      } else {  // the batched kernel: the same pass, its register allocation kept
+        T* M = half == 0 ? R : W;
+        T a[RPL], b[RPL];
+  #pragma unroll
+        for (int i = 0; i < RPL; i++) {
+          const int row = sub + LPS * i;
+          const bool ok = row < m && slot < L;
+          a[i] = ok ? M[slot * LDR + row] : zero_of(T());
+          b[i] = ok ? M[(n1 + slot) * LDR + row] : zero_of(T());
+        }
+        __syncthreads();
+        // LDS exchange buffers (aliasing R and W_P): per half two parities of 32 slots x 64 rows
+        T* ringh = lds + half * (4 * 32 * kMaxPivot / 2);
+        const double sr = slot < L ? (double)sg[slot] : 0.0;
+        double ss = slot < L ? (double)sg[n1 + slot] : 0.0;  // sign of the held second-block column (half 0)
+        for (int q = 0; q <= L; q++) {
+          if (half == 0 && q < L && slot < L) {
+            double arr = 0.0, ass = 0.0, are = 0.0, aim = 0.0;
+  #pragma unroll
             for (int i = 0; i < RPL; i++) {
-              const T f = phase_mul(pr, pi, a[i]), g = b[i];
-              a[i] = lin2(cs, f, -sigma * sn, g);
-              b[i] = lin2(sn, f, cs, g);
+              arr += abs2(a[i]);
+              ass += abs2(b[i]);
+              cdot(a[i], b[i], are, aim);
             }
-            cnt += (sub == 0);
-          } else if (rc < 0 && sub == 0) {
-            atomicOr(&s_bad, 1);
+            arr = slot_sum<LPS>(arr);
+            ass = slot_sum<LPS>(ass);
+            are = slot_sum<LPS>(are);
+            if (CPLX) aim = slot_sum<LPS>(aim);
+            const double sigma = sr * ss;
+            double cs, sn, pr, pi;
+            const int rc = pair_rotation(arr, ass, are, aim, CPLX, sigma, tol, &cs, &sn, &pr, &pi);
+            if (sub == 0) {
+              prm[q & 1][slot][0] = cs;
+              prm[q & 1][slot][1] = sn;
+              prm[q & 1][slot][2] = -sigma * sn;
+              prm[q & 1][slot][3] = pr;
+              prm[q & 1][slot][4] = pi;
+              prc[q & 1][slot] = rc > 0;
+            }
+            if (rc > 0) {
+  #pragma unroll
+              for (int i = 0; i < RPL; i++) {
+                const T f = phase_mul(pr, pi, a[i]), g = b[i];
+                a[i] = lin2(cs, f, -sigma * sn, g);
+                b[i] = lin2(sn, f, cs, g);
+              }
+              cnt += (sub == 0);
+            } else if (rc < 0 && sub == 0) {
+              atomicOr(&s_bad, 1);
+            }
+          } else if (half == 1 && q >= 1 && slot < L && prc[(q - 1) & 1][slot]) {
+            const double* pp = prm[(q - 1) & 1][slot];
+            const double cs = pp[0], sn = pp[1], msn = pp[2], pr = pp[3], pi = pp[4];
+  #pragma unroll
+            for (int i = 0; i < RPL; i++) {
+              const T u = phase_mul(pr, pi, a[i]), w = b[i];
+              a[i] = lin2(cs, u, msn, w);
+              b[i] = lin2(sn, u, cs, w);
+            }
           }
-        } else if (half == 1 && q >= 1 && slot < L && prc[(q - 1) & 1][slot]) {
-          const double* pp = prm[(q - 1) & 1][slot];
-          const double cs = pp[0], sn = pp[1], msn = pp[2], pr = pp[3], pi = pp[4];
-#pragma unroll
-          for (int i = 0; i < RPL; i++) {
-            const T u = phase_mul(pr, pi, a[i]), w = b[i];
-            a[i] = lin2(cs, u, msn, w);
-            b[i] = lin2(sn, u, cs, w);
+          // move of the held column: half 0 into round q + 1, half 1 into round q
+          const int mq = half == 0 ? q + 1 : q;
+          const int bit = (mq >= 1 && mq < L) ? __builtin_ctz(mq) : -1;
+          const int lx = bit >= 0 ? (LPS << bit) : 0;
+          if (lx == 8) {
+            if (half == 0) ss = xor8_of(ss);
+  #pragma unroll
+            for (int i = 0; i < RPL; i++) b[i] = xor8_of(b[i]);
+          } else if (lx > 0 && lx < 64) {
+            const int addr = ((tid & 63) ^ lx) << 2;
+            if (half == 0) ss = bperm_of(ss, addr);
+  #pragma unroll
+            for (int i = 0; i < RPL; i++) b[i] = bperm_of(b[i], addr);
           }
-        }
-        // move of the held column: half 0 into round q + 1, half 1 into round q
-        const int mq = half == 0 ? q + 1 : q;
-        const int bit = (mq >= 1 && mq < L) ? __builtin_ctz(mq) : -1;
-        const int lx = bit >= 0 ? (LPS << bit) : 0;
-        if (lx == 8) {
-          if (half == 0) ss = xor8_of(ss);
-#pragma unroll
-          for (int i = 0; i < RPL; i++) b[i] = xor8_of(b[i]);
-        } else if (lx > 0 && lx < 64) {
-          const int addr = ((tid & 63) ^ lx) << 2;
-          if (half == 0) ss = bperm_of(ss, addr);
-#pragma unroll
-          for (int i = 0; i < RPL; i++) b[i] = bperm_of(b[i], addr);
-        }
-        double2* ring = reinterpret_cast<double2*>(ringh + (q & 1) * (32 * kMaxPivot));
-        if (lx >= 64) {
-          if (half == 0 && sub == 0) ring_sg[q & 1][slot] = (int)ss;
-          if constexpr (CPLX) {
-#pragma unroll
-            for (int j = 0; j < RPL; j++) ring[(j * 32 + slot) * LPS + sub] = b[j];
-          } else {
-#pragma unroll
-            for (int j = 0; j < RPL / 2; j++) ring[(j * 32 + slot) * LPS + sub] = double2{b[2 * j], b[2 * j + 1]};
+          double2* ring = reinterpret_cast<double2*>(ringh + (q & 1) * (32 * kMaxPivot));
+          if (lx >= 64) {
+            if (half == 0 && sub == 0) ring_sg[q & 1][slot] = (int)ss;
+            if constexpr (CPLX) {
+  #pragma unroll
+              for (int j = 0; j < RPL; j++) ring[(j * 32 + slot) * LPS + sub] = b[j];
+            } else {
+  #pragma unroll
+              for (int j = 0; j < RPL / 2; j++) ring[(j * 32 + slot) * LPS + sub] = double2{b[2 * j], b[2 * j + 1]};
+            }
+          }
+          __syncthreads();
+          if (lx >= 64) {
+            const int from = slot ^ (1 << bit);
+            if (half == 0) ss = (double)ring_sg[q & 1][from];
+            if constexpr (CPLX) {
+  #pragma unroll
+              for (int j = 0; j < RPL; j++) b[j] = ring[(j * 32 + from) * LPS + sub];
+            } else {
+  #pragma unroll
+              for (int j = 0; j < RPL / 2; j++) {
+                const double2 v = ring[(j * 32 + from) * LPS + sub];
+                b[2 * j] = v.x;
+                b[2 * j + 1] = v.y;
+              }
+            }
           }
         }
         __syncthreads();
-        if (lx >= 64) {
-          const int from = slot ^ (1 << bit);
-          if (half == 0) ss = (double)ring_sg[q & 1][from];
-          if constexpr (CPLX) {
-#pragma unroll
-            for (int j = 0; j < RPL; j++) b[j] = ring[(j * 32 + from) * LPS + sub];
-          } else {
-#pragma unroll
-            for (int j = 0; j < RPL / 2; j++) {
-              const double2 v = ring[(j * 32 + from) * LPS + sub];
-              b[2 * j] = v.x;
-              b[2 * j + 1] = v.y;
+        // write the columns back: slot k holds second-block column k ^ gray(L - 1) = k ^ (L / 2)
+        const int sfin = slot ^ (L >> 1);
+        if (slot < L) {
+  #pragma unroll
+          for (int i = 0; i < RPL; i++) {
+            const int row = sub + LPS * i;
+            if (row < m) {
+              M[slot * LDR + row] = a[i];
+              M[(n1 + sfin) * LDR + row] = b[i];
             }
-          }
-        }
-      }
-      __syncthreads();
-      // write the columns back: slot k holds second-block column k ^ gray(L - 1) = k ^ (L / 2)
-      const int sfin = slot ^ (L >> 1);
-      if (slot < L) {
-#pragma unroll
-        for (int i = 0; i < RPL; i++) {
-          const int row = sub + LPS * i;
-          if (row < m) {
-            M[slot * LDR + row] = a[i];
-            M[(n1 + sfin) * LDR + row] = b[i];
           }
         }
       }
