@@ -30,7 +30,8 @@ def _run(entry, G, J, **kw):
 @pytest.mark.parametrize("precision", [0, 1])
 def test_noalloc_matches_allocating_entry_point(precision):
     cases = [jjgen.make(300, True, 120, 1e-6, 1.0, seed=5150),   # first call: larger, complex
-             jjgen.make(150, False, 70, 1e-8, 1.0, seed=5151)]   # second call: smaller, real
+             jjgen.make(150, False, 70, 1e-8, 1.0, seed=5151),   # second call: smaller, real
+             jjgen.make(64, False, 32, 1e-3, 1e3, seed=5152)]    # third: n <= 64, the direct path in FP64
     for G, J, _ in cases:
         st0, l0, V0, i0 = _run("jjacobi_solve_ex", G, J, precision=precision)
         st1, l1, V1, i1 = _run("jjacobi_solve_noalloc", G, J, precision=precision)
