@@ -826,7 +826,7 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
       } else {  // the batched kernel: the same pass, its register allocation kept
         T* M = half == 0 ? R : W;
         T a[RPL], b[RPL];
-  #pragma unroll
+#pragma unroll
         for (int i = 0; i < RPL; i++) {
           const int row = sub + LPS * i;
           const bool ok = row < m && slot < L;
@@ -841,7 +841,7 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
         for (int q = 0; q <= L; q++) {
           if (half == 0 && q < L && slot < L) {
             double arr = 0.0, ass = 0.0, are = 0.0, aim = 0.0;
-  #pragma unroll
+#pragma unroll
             for (int i = 0; i < RPL; i++) {
               arr += abs2(a[i]);
               ass += abs2(b[i]);
@@ -863,7 +863,7 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
               prc[q & 1][slot] = rc > 0;
             }
             if (rc > 0) {
-  #pragma unroll
+#pragma unroll
               for (int i = 0; i < RPL; i++) {
                 const T f = phase_mul(pr, pi, a[i]), g = b[i];
                 a[i] = lin2(cs, f, -sigma * sn, g);
@@ -876,7 +876,7 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
           } else if (half == 1 && q >= 1 && slot < L && prc[(q - 1) & 1][slot]) {
             const double* pp = prm[(q - 1) & 1][slot];
             const double cs = pp[0], sn = pp[1], msn = pp[2], pr = pp[3], pi = pp[4];
-  #pragma unroll
+#pragma unroll
             for (int i = 0; i < RPL; i++) {
               const T u = phase_mul(pr, pi, a[i]), w = b[i];
               a[i] = lin2(cs, u, msn, w);
@@ -889,22 +889,22 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
           const int lx = bit >= 0 ? (LPS << bit) : 0;
           if (lx == 8) {
             if (half == 0) ss = xor8_of(ss);
-  #pragma unroll
+#pragma unroll
             for (int i = 0; i < RPL; i++) b[i] = xor8_of(b[i]);
           } else if (lx > 0 && lx < 64) {
             const int addr = ((tid & 63) ^ lx) << 2;
             if (half == 0) ss = bperm_of(ss, addr);
-  #pragma unroll
+#pragma unroll
             for (int i = 0; i < RPL; i++) b[i] = bperm_of(b[i], addr);
           }
           double2* ring = reinterpret_cast<double2*>(ringh + (q & 1) * (32 * kMaxPivot));
           if (lx >= 64) {
             if (half == 0 && sub == 0) ring_sg[q & 1][slot] = (int)ss;
             if constexpr (CPLX) {
-  #pragma unroll
+#pragma unroll
               for (int j = 0; j < RPL; j++) ring[(j * 32 + slot) * LPS + sub] = b[j];
             } else {
-  #pragma unroll
+#pragma unroll
               for (int j = 0; j < RPL / 2; j++) ring[(j * 32 + slot) * LPS + sub] = double2{b[2 * j], b[2 * j + 1]};
             }
           }
@@ -913,10 +913,10 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
             const int from = slot ^ (1 << bit);
             if (half == 0) ss = (double)ring_sg[q & 1][from];
             if constexpr (CPLX) {
-  #pragma unroll
+#pragma unroll
               for (int j = 0; j < RPL; j++) b[j] = ring[(j * 32 + from) * LPS + sub];
             } else {
-  #pragma unroll
+#pragma unroll
               for (int j = 0; j < RPL / 2; j++) {
                 const double2 v = ring[(j * 32 + from) * LPS + sub];
                 b[2 * j] = v.x;
@@ -929,7 +929,7 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
         // write the columns back: slot k holds second-block column k ^ gray(L - 1) = k ^ (L / 2)
         const int sfin = slot ^ (L >> 1);
         if (slot < L) {
-  #pragma unroll
+#pragma unroll
           for (int i = 0; i < RPL; i++) {
             const int row = sub + LPS * i;
             if (row < m) {
