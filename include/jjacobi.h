@@ -85,8 +85,10 @@ typedef struct jj_opts {
                                with the block width where the width is tuned (whole
                                solves of both variants up to n = 1024), else 0 */
   int precision;         /* 0: FP64 throughout; 1: mixed (FP32 Gram in pre-sweeps) */
-  double mixed_switch;   /* mixed: sweeps whose max scaled off-diagonal is below this
-                            run in FP64; 0: 1e-5 */
+  double mixed_switch;   /* mixed: the solve leaves its FP32-Gram sweeps after a sweep
+                            whose max scaled off-diagonal is below this; 0: 0.1
+                            (measured: the FP32 Gram's error slows the last,
+                            quadratically converging sweeps, not the earlier ones) */
   int strategy;          /* 0: round-robin block pairing (Section 4.2);
                             1: modulus pairing (Section 4.1) */
   int profile;           /* 1: time every kernel launch with HIP events on the stream

@@ -689,7 +689,7 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
   // scaled off-diagonal falls below mixed_switch; those sweeps use a rotation
   // threshold above FP32 rounding noise and never declare convergence.
   bool mixed = o.precision == 1;
-  const double mix_switch = o.mixed_switch > 0.0 ? o.mixed_switch : 1e-5;
+  const double mix_switch = o.mixed_switch > 0.0 ? o.mixed_switch : 0.1;
   const double tol_mix = std::max(tol, std::ldexp(1.0, -20));
   int mixed_sweeps = 0, mixed_resolved = 0;
   int status = JJ_NOT_CONVERGED, sweep = 0;
@@ -1323,7 +1323,7 @@ static int solve_batch(int count, const int* dtype, void* const* G, const signed
   up(d_active_count, &nactive, sizeof(int));
   // mixed precision (reading as for single solves): FP32-Gram sweeps per problem
   const bool mixed = o.precision == 1;
-  const double mix_switch = o.mixed_switch > 0.0 ? o.mixed_switch : 1e-5;
+  const double mix_switch = o.mixed_switch > 0.0 ? o.mixed_switch : 0.1;
   std::vector<int> prec0(count, mixed ? 1 : 0), msw0(count, 0);
   up(d_prec, prec0.data(), count * sizeof(int));
   up(d_msw, msw0.data(), count * sizeof(int));
@@ -1543,7 +1543,7 @@ void jjacobi_default_opts(jj_opts* o) {
   o->block_width = 0;  // library choice (tuned where it matters)
   o->inner_max_sweeps = 12;
   o->inner_mode = -1;  // library choice
-  o->mixed_switch = 1e-5;
+  o->mixed_switch = 0.1;
 }
 
 int jjacobi_solve_ex(int dtype, void* G, const signed char* J, int n, int ldg, double* lambda, void* V, int ldv,
