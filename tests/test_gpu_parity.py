@@ -70,7 +70,7 @@ def test_config1_parity():
 
 
 @pytest.mark.parametrize("cplx", [False, True])
-@pytest.mark.parametrize("n", [2, 3, 17, 33, 63, 64, 65, 100, 127, 130, 200])
+@pytest.mark.parametrize("n", [2, 3, 4, 8, 16, 17, 32, 33, 63, 64, 65, 100, 127, 130, 200])
 def test_ragged_sizes(cplx, n):
     G, J, lam = jjgen.make(n, cplx, (2 * n) // 5, 1e-4, 1e2, seed=300 + n + (1000 if cplx else 0))
     lg, V, info = gpu_solve(G, J)
