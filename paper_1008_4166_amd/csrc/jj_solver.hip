@@ -561,13 +561,13 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
     c.take<signed char>((size_t)P.nbl * kMaxPivot);
     c.take<int>(P.nbl);
     c.take<int>(P.nbl);
+    c.take<int>(n);
+    c.take<signed char>(n);
     c.take<double>((size_t)nb_piv * nch * kMaxPivot * kMaxPivot * (cplx ? 2 : 1));
     c.take<double>((size_t)nb_piv * kMaxPivot * kMaxPivot * (cplx ? 2 : 1));
     c.take<int>(nb_piv);
     c.take<int>((size_t)std::max(P.nsteps, 1) * h + P.nbl);
     c.take<SweepStats>(1);
-    c.take<int>(n);
-    c.take<signed char>(n);
     c.take<double>(n);
     c.take<int>(n);
     if (three) {
@@ -598,6 +598,8 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
   signed char* d_dsg = c.take<signed char>((size_t)P.nbl * kMaxPivot);
   int* d_dm = c.take<int>(P.nbl);
   int* d_dnf = c.take<int>(P.nbl);
+  int* d_colmap = c.take<int>(n);
+  signed char* d_sgn = c.take<signed char>(n);
   double* d_part = c.take<double>((size_t)nb_piv * nch * kMaxPivot * kMaxPivot * (cplx ? 2 : 1));
   double* d_W = c.take<double>((size_t)nb_piv * kMaxPivot * kMaxPivot * (cplx ? 2 : 1));
   int* d_rot = c.take<int>(nb_piv);
@@ -606,8 +608,6 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
   int* d_promote = c.take<int>((size_t)std::max(P.nsteps, 1) * h + P.nbl);
   int* d_promote_diag = d_promote + (size_t)std::max(P.nsteps, 1) * h;
   SweepStats* d_st = c.take<SweepStats>(1);
-  int* d_colmap = c.take<int>(n);
-  signed char* d_sgn = c.take<signed char>(n);
   double* d_d = c.take<double>(n);
   int* d_rank = c.take<int>(n);
   // three-level pivots: sub-pivot and inner tables, Gram partials, R slots
@@ -644,19 +644,33 @@ static int solve_one(int dtype, void* Gv, const signed char* J, int n, int ldg, 
     up(d_inf, T3.inf.data(), T3.inf.size() * sizeof(int));
   }
 
-  if (P.nsteps > 0 && !three) {
-    ck(hipMemcpyAsync(d_cols, P.cols.data(), P.cols.size() * sizeof(int), hipMemcpyHostToDevice, stream), "H2D");
-    ck(hipMemcpyAsync(d_sg, P.sgp.data(), P.sgp.size(), hipMemcpyHostToDevice, stream), "H2D");
-    ck(hipMemcpyAsync(d_m, P.m.data(), P.m.size() * sizeof(int), hipMemcpyHostToDevice, stream), "H2D");
-    ck(hipMemcpyAsync(d_nf, P.nfirst.data(), P.nfirst.size() * sizeof(int), hipMemcpyHostToDevice, stream),
-       "H2D");
+  // The plan's tables lie back to back in the workspace (pair tables, diagonal-
+  // pass tables, column map and signs): they go up in one copy from a host
+  // image of that span (the alignment gaps and tables not used are zero).  The
+  // image outlives the copy: it is freed when the solve returns, after the
+  // stream has been synchronised.
+  std::vector<char> img;
+  {
+    char* lo = reinterpret_cast<char*>(d_cols);
+    const size_t span = static_cast<size_t>(reinterpret_cast<char*>(d_sgn + n) - lo);
+    img.assign(span, 0);
+    auto put = [&](const void* dst, const void* src, size_t bytes) {
+      if (bytes) std::memcpy(img.data() + (reinterpret_cast<const char*>(dst) - lo), src, bytes);
+    };
+    if (P.nsteps > 0 && !three) {
+      put(d_cols, P.cols.data(), P.cols.size() * sizeof(int));
+      put(d_sg, P.sgp.data(), P.sgp.size());
+      put(d_m, P.m.data(), P.m.size() * sizeof(int));
+      put(d_nf, P.nfirst.data(), P.nfirst.size() * sizeof(int));
+    }
+    put(d_dcols, dcols.data(), dcols.size() * sizeof(int));
+    put(d_dsg, dsg.data(), dsg.size());
+    put(d_dm, dm.data(), dm.size() * sizeof(int));
+    put(d_dnf, dnf.data(), dnf.size() * sizeof(int));
+    put(d_colmap, P.colmap.data(), n * sizeof(int));
+    put(d_sgn, P.sgn.data(), n);
+    ck(hipMemcpyAsync(lo, img.data(), span, hipMemcpyHostToDevice, stream), "H2D");
   }
-  ck(hipMemcpyAsync(d_dcols, dcols.data(), dcols.size() * sizeof(int), hipMemcpyHostToDevice, stream), "H2D");
-  ck(hipMemcpyAsync(d_dsg, dsg.data(), dsg.size(), hipMemcpyHostToDevice, stream), "H2D");
-  ck(hipMemcpyAsync(d_dm, dm.data(), dm.size() * sizeof(int), hipMemcpyHostToDevice, stream), "H2D");
-  ck(hipMemcpyAsync(d_dnf, dnf.data(), dnf.size() * sizeof(int), hipMemcpyHostToDevice, stream), "H2D");
-  ck(hipMemcpyAsync(d_colmap, P.colmap.data(), n * sizeof(int), hipMemcpyHostToDevice, stream), "H2D");
-  ck(hipMemcpyAsync(d_sgn, P.sgn.data(), n, hipMemcpyHostToDevice, stream), "H2D");
 
   Profiler prof;
   prof.on = o.profile != 0 && !noalloc;
