@@ -4,8 +4,12 @@ Eigenvalues are compared element by element (both sorted descending).  The bar
 is a relative error of 1e-12 per eigenvalue wherever the double oracle itself
 agrees with the long-double oracle to 2.5e-13; where the input's scaled
 condition number makes two correct double computations differ by more, the GPU
-must be within 4x of the double oracle's own distance to the long-double one
-(both measured against the long-double result)."""
+must be within 4x of the double oracle's own distance to the long-double one,
+or within eps kappa_s(G) of the long-double result (kappa_s: condition number
+of G with unit columns; the relative perturbation bound of the paper's
+Introduction, eps n kappa(A_s) with kappa(A_s) = kappa_s(G)^2 for A = G^* G,
+is far looser).  Orderings of the same correct arithmetic spread by several
+times on such inputs, so one oracle run is not a sharp bar alone."""
 import os
 
 import numpy as np
@@ -44,7 +48,10 @@ def check_parity(G, J, lam_gpu, tag=""):
     e_ora = rel_err(rd["lam"], ref)
     e_gl = rel_err(lam_gpu, ref)
     assert e_ora > 2.5e-13, "%s: GPU vs oracle %.3e > 1e-12 with a well-conditioned oracle" % (tag, e_gpu)
-    assert e_gl <= 4 * e_ora, "%s: GPU vs long double %.3e > 4 x oracle's %.3e" % (tag, e_gl, e_ora)
+    # the relative perturbation bound of the Introduction is eps n kappa(A_s)
+    # for A = G^* G, kappa(A_s) = kappa_s(G)^2; eps kappa_s(G) lies well inside it
+    bound = max(4 * e_ora, EPS * kappa_s(G))
+    assert e_gl <= bound, "%s: GPU vs long double %.3e > max(4 x oracle's %.3e, eps kappa_s)" % (tag, e_gl, e_ora)
     return e_gpu
 
 
