@@ -67,16 +67,40 @@ __device__ __forceinline__ void atomic_max_nonneg(unsigned long long* addr, doub
 // ---------------------------------------------------------------------------
 // Gram partials.  Grid (chunks, P), 256 threads.  Chunk ch covers rows
 // [ch*rows_per_chunk, min(n, (ch+1)*rows_per_chunk)).  The chunk is staged
-// through LDS in blocks of 64 rows: each wave loads whole columns (lane = row,
-// 512 contiguous bytes per instruction) into a column-major LDS block with
-// column stride 68, while the previous block is multiplied; the MFMA operands
-// are then read from LDS (lane (c16, g) takes row 4kk + g of column 16T + c16,
-// word offset 8 c16 + 2g modulo the 64 banks).  Wave w accumulates all 10 upper
-// 16x16 tiles over rows 16w..16w+15 of every block; the four waves are reduced
-// through LDS in a fixed order and the partial is written per chunk.
+// through LDS in blocks of 32 rows by load-to-LDS instructions
+// (global_load_lds_dwordx4: each lane fetches 16 bytes, one row pair of one
+// column, and the instruction writes the 64 lanes' data to 1 KiB of LDS at
+// base + 16 lane without passing through registers).  Three blocks rotate, two
+// in flight while the third is multiplied.  In a block, column c occupies 32
+// doubles and its row pair q sits in slot q ^ (c % 16): the lane that fills a
+// slot fetches the row pair the slot holds, so each column is still read whole
+// and contiguous, and an MFMA operand read (lane (c16, g) takes row r of column
+// 16T + c16, word offset 4 ((r/2) ^ c16) + 2 (r%2) modulo the 64 banks) touches
+// every bank exactly twice.  Padding columns and rows past the chunk read a
+// zero pair; for an odd row count the chunk's last row, whose pair straddles
+// the end, is written separately.  Wave w accumulates all 10 upper 16x16 tiles
+// over rows 8w..8w+7 of every block; the four waves are reduced through LDS in
+// a fixed order and the partial is written per chunk.  Measured at n = 4096
+// (64 pairs of 64 columns, 8 chunks): 34.1 -> 28.9 us per launch against
+// staging the blocks through registers; more blocks in flight (4 to 7) were
+// slower.
 // ---------------------------------------------------------------------------
-constexpr int kGramRows = 64;
-constexpr int kGramLdc = 68;
+constexpr int kGramRows = 32;                        // rows per staged block
+constexpr int kGramBufs = 3;                         // staged blocks
+constexpr int kGramLpc = kGramRows / 2;              // lanes per column in one load instruction
+constexpr int kGramCpi = 64 / kGramLpc;              // columns per load instruction
+constexpr int kGramIpw = kMaxPivot / kGramCpi / 4;   // load instructions per wave per block
+constexpr int kGramSmem = kGramBufs * kMaxPivot * kGramRows;
+static_assert(kGramSmem >= 2 * 10 * 64 * 4, "the wave reduction reuses the staging blocks");
+static_assert(kGramBufs == 3, "the loads waited for: one block issued later");
+
+__device__ double gram_zero_pair[2];  // the source of padding: never written
+
+typedef __attribute__((address_space(3))) void* lds_void;
+
+// s_waitcnt with vmcnt = v (expcnt and lgkmcnt left alone): the field layout of
+// gfx9 encodings, vmcnt bits 3:0 and 15:14
+#define JJ_WAIT_VM(v) __builtin_amdgcn_s_waitcnt(((v) & 15) | (((v) >> 4) << 14) | 0xF70)
 
 template <bool F32>
 __device__ __forceinline__ void gram_real_body(const double* __restrict__ G0, int ldg0, int n0,
@@ -88,7 +112,6 @@ __device__ __forceinline__ void gram_real_body(const double* __restrict__ G0, in
   SweepStats* stp = nullptr;
   if (!batch_resolve(bt, slot, p, Gm, ldg, n, stp)) return;
   if (ch > 0 && ch * rows_per_chunk >= n) return;  // chunk beyond this problem's rows
-  const gdbl* G = as_global(Gm);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int c16 = lane & 15, g = lane >> 4;
   const int m = mlist[p];
@@ -98,61 +121,80 @@ __device__ __forceinline__ void gram_real_body(const double* __restrict__ G0, in
   const int r1 = min(n, r0 + rows_per_chunk);
   const int nblk = (r1 - r0 + kGramRows - 1) / kGramRows;
 
-  // loader: wave w stages columns w + 4i (i < 16), lane = row of the block;
-  // loads are unconditional (a padding column reads the pivot's first column,
-  // a row past the chunk its last row) and zeroed by a 0/1 factor (the matrix
-  // is finite: non-finite input is rejected before the sweeps)
-  const int c0 = cols[p * kMaxPivot];
-  size_t coff[16];
-  unsigned okbits = 0;
+  // loader: instruction j of wave w fills columns kGramCpi (kGramIpw w + j) ..
+  // + kGramCpi - 1; this lane, column col, fetches row pair q of each block
+  const double* colp[kGramIpw];
+  int qrow[kGramIpw];
 #pragma unroll
-  for (int i = 0; i < 16; i++) {
-    const int c = wave + 4 * i;
-    const int pc = c < m ? cols[p * kMaxPivot + c] : -1;
-    okbits |= pc >= 0 ? (1u << i) : 0u;
-    coff[i] = (size_t)(pc >= 0 ? pc : c0) * ldg;
+  for (int j = 0; j < kGramIpw; j++) {
+    const int col = kGramCpi * (kGramIpw * wave + j) + lane / kGramLpc;
+    qrow[j] = 2 * ((lane % kGramLpc) ^ (col % kGramLpc));
+    colp[j] = col < m ? Gm + (size_t)cols[p * kMaxPivot + col] * ldg : nullptr;
   }
-  double ld[16];
-  auto load_block = [&](int b) {
-    const int row = r0 + b * kGramRows + lane;
-    const unsigned ok = row < r1 ? okbits : 0u;
-    const int rl = min(row, r1 - 1);
+  auto issue = [&](int b, int buf) {
+    double* S = smem + buf * (kMaxPivot * kGramRows);
 #pragma unroll
-    for (int i = 0; i < 16; i++) ld[i] = G[coff[i] + rl] * ((ok >> i) & 1u ? 1.0 : 0.0);
-  };
-  auto store_block = [&](int buf) {
-    double* S = smem + buf * (kMaxPivot * kGramLdc);
-#pragma unroll
-    for (int i = 0; i < 16; i++) S[(wave + 4 * i) * kGramLdc + lane] = ld[i];
+    for (int j = 0; j < kGramIpw; j++) {
+      const int row = r0 + b * kGramRows + qrow[j];
+      const double* src = (colp[j] != nullptr && row + 1 < r1) ? colp[j] + row : gram_zero_pair;
+      __builtin_amdgcn_global_load_lds(src, (lds_void)(S + (kGramIpw * wave + j) * (kGramCpi * kGramRows)), 16, 0, 0);
+    }
   };
 
   typename GAcc<F32>::T ac[10];
 #pragma unroll
   for (int t = 0; t < 10; t++) ac[t] = GAcc<F32>::zero();
-  load_block(0);
-  store_block(0);
-  __syncthreads();
-  for (int b = 0; b < nblk; b++) {
-    if (b + 1 < nblk) load_block(b + 1);  // in flight during the MFMAs below
-    const double* S = smem + (b & 1) * (kMaxPivot * kGramLdc);
-#pragma unroll
-    for (int kk = 0; kk < 4; kk++) {
-      const int row = 16 * wave + 4 * kk + g;
-      double xt[4];
-#pragma unroll
-      for (int T = 0; T < 4; T++) xt[T] = S[(16 * T + c16) * kGramLdc + row];
-      int t = 0;
-#pragma unroll
-      for (int I = 0; I < 4; I++)
-#pragma unroll
-        for (int J = I; J < 4; J++) {
-          if (J < nt) ac[t] = GAcc<F32>::mma(xt[I], xt[J], ac[t]);
-          t++;
+  for (int b = 0; b < kGramBufs - 1 && b < nblk; b++) issue(b, b);
+  // full: all four column tiles in use, no branch around the MFMAs (a
+  // conditional MFMA compiles to a block of its own with a wait for its operands)
+  auto rows = [&](auto full) {
+    int buf = 0;
+    for (int b = 0; b < nblk; b++) {
+      // this wave's loads of block b have landed once at most the later
+      // blocks' (one here) are in flight; the barrier then covers every wave's.
+      // A bare s_barrier: __syncthreads() is a release fence that would wait
+      // for all loads in flight and undo the prefetch.
+      if (b + 1 < nblk) JJ_WAIT_VM(kGramIpw);
+      else JJ_WAIT_VM(0);
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_s_barrier();
+      asm volatile("" ::: "memory");
+      const double* S = smem + buf * (kMaxPivot * kGramRows);
+      if (b == nblk - 1 && ((r1 - r0) & 1)) {
+        // odd row count: the last row's pair straddles the end and was loaded
+        // as zeros; wave 0 writes the row itself (lane = column)
+        if (wave == 0 && lane < m) {
+          const int rr = r1 - 1 - (r0 + b * kGramRows);
+          smem[buf * (kMaxPivot * kGramRows) + lane * kGramRows + 2 * ((rr >> 1) ^ (lane % kGramLpc)) + (rr & 1)] =
+              as_global(Gm)[(size_t)cols[p * kMaxPivot + lane] * ldg + r1 - 1];
         }
+        __syncthreads();
+      }
+      // the buffer of block b - 1, free since the barrier above
+      if (b + kGramBufs - 1 < nblk) issue(b + kGramBufs - 1, buf == 0 ? kGramBufs - 1 : buf - 1);
+#pragma unroll
+      for (int kk = 0; kk < kGramRows / 16; kk++) {
+        const int r = (kGramRows / 4) * wave + 4 * kk + g;
+        double xt[4];
+#pragma unroll
+        for (int T = 0; T < 4; T++) xt[T] = S[(16 * T + c16) * kGramRows + 2 * ((r >> 1) ^ c16) + (r & 1)];
+        int t = 0;
+#pragma unroll
+        for (int I = 0; I < 4; I++)
+#pragma unroll
+          for (int J = I; J < 4; J++) {
+            if (decltype(full)::value || J < nt) ac[t] = GAcc<F32>::mma(xt[I], xt[J], ac[t]);
+            t++;
+          }
+      }
+      buf = buf == kGramBufs - 1 ? 0 : buf + 1;
     }
-    if (b + 1 < nblk) store_block((b + 1) & 1);
-    __syncthreads();
-  }
+  };
+  if (nt == 4)
+    rows(std::true_type{});
+  else
+    rows(std::false_type{});
+  __syncthreads();  // every wave is done with the blocks: the reduction reuses them
   // fixed-order reduction of the four waves: (w0 + w2) + (w1 + w3), through LDS
   d4 acc[10];
 #pragma unroll
@@ -189,7 +231,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_real(const double* __restrict__
                                                      const int* __restrict__ cols, const int* __restrict__ mlist,
                                                      int rows_per_chunk, double* __restrict__ part, Batch bt,
                                                      const int* __restrict__ only) {
-  __shared__ double smem[2 * kMaxPivot * kGramLdc];  // two staged blocks; then the wave reduction
+  __shared__ double smem[kGramSmem];  // the staged blocks; then the wave reduction
   int slot, ch;
   xcd_slot_chunk(slot, ch);
   if (only != nullptr && !only[slot]) return;  // a re-solve launch: this pivot was solved
@@ -209,7 +251,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_real_sel(const double* __restri
                                                          const int* __restrict__ cols, const int* __restrict__ mlist,
                                                          int rows_per_chunk, double* __restrict__ part, Batch bt,
                                                          const int* __restrict__ f64) {
-  __shared__ double smem[2 * kMaxPivot * kGramLdc];
+  __shared__ double smem[kGramSmem];
   int slot, ch;
   xcd_slot_chunk(slot, ch);
   if (gram_slot_f64(bt, slot, f64))
@@ -323,18 +365,25 @@ __global__ __launch_bounds__(256, 4) void k_update_f64(double* __restrict__ G0, 
 // Complex Hermitian (complex128, interleaved).  A = X^H X is formed from real
 // MFMA products: Re A = Xr^T Xr + Xi^T Xi, Im A = Xr^T Xi - Xi^T Xr.
 // ---------------------------------------------------------------------------
-// Complex Gram: the same staging with 32-row blocks of (re, im) pairs (512
-// contiguous bytes per column and block, two columns per wave instruction),
-// column stride 36 pairs in LDS (16-byte operand reads spread over the banks:
-// 16 c16 + 4g words).  Each upper 16x16 tile takes three real MFMA products
+// Complex Gram: the same load-to-LDS staging with 16-row blocks of (re, im)
+// pairs (one 16-byte element per lane: 16 lanes per column, four columns per
+// instruction) and row r of column c in slot r ^ (c % 16), so that a 16-byte
+// operand read (word offset 4 (r ^ c16) modulo the 64 banks) touches every bank
+// four times, the least for 64 such reads; no row pair straddles the end of
+// the chunk.  Each upper 16x16 tile takes three real MFMA products
 // (Gauss): P1 = Xr_I^T Xr_J, P2 = Xi_I^T Xi_J, P3 = (Xr_I - Xi_I)^T (Xr_J + Xi_J),
 // Re A = P1 + P2, Im A = P3 - P1 + P2 (Im A = Xr^T Xi - Xi^T Xr).  The rounding
 // error of every entry stays below a small multiple of eps ||x_i|| ||x_j||, the
 // column-scaled bound the off-diagonal test and the rotations rely on.  Wave w
 // takes row half w >> 1 of every block and tile set w & 1 (upper tiles 0-4 or
 // 5-9 in row-major order); the two row halves are added in a fixed order.
-constexpr int kGramRowsC = 32;
-constexpr int kGramLdcC = 36;
+constexpr int kGramRowsC = 16;                                // rows per staged block
+constexpr int kGramBufsC = 3;                                 // staged blocks in rotation
+constexpr int kGramIpwC = kMaxPivot * kGramRowsC / 64 / 4;    // load instructions per wave per block
+static_assert(kGramBufsC >= 2 && kGramBufsC <= 4, "the loads waited for: at most two blocks issued later");
+constexpr int kGramSmemC = kGramBufsC * kMaxPivot * kGramRowsC > 2 * 15 * 64 * 2
+                               ? kGramBufsC * kMaxPivot * kGramRowsC
+                               : 2 * 15 * 64 * 2;             // staged blocks, or the reduction (d4 = 2 dv2)
 
 template <int TS, bool FULL, bool F32>
 __device__ __forceinline__ void gram3m_tiles(const double (&xr)[4], const double (&xi)[4], int nt,
@@ -382,7 +431,6 @@ __device__ __forceinline__ void gram_cplx_body(const double* __restrict__ G0, in
   SweepStats* stp = nullptr;
   if (!batch_resolve(bt, slot, p, Gm, ldg, n, stp)) return;
   if (ch > 0 && ch * rows_per_chunk >= n) return;  // chunk beyond this problem's rows
-  const gdbl2* G = as_global2(Gm);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int c16 = lane & 15, g = lane >> 4;
   const int m = mlist[p];
@@ -392,31 +440,24 @@ __device__ __forceinline__ void gram_cplx_body(const double* __restrict__ G0, in
   const int r1 = min(n, r0 + rows_per_chunk);
   const int nblk = (r1 - r0 + kGramRowsC - 1) / kGramRowsC;
 
-  // loader: wave w, instruction i stages column 2 (w + 4i) + lane / 32, row lane % 32;
-  // unconditional clamped loads, padding zeroed by a 0/1 factor (finite matrix)
-  const int c0 = cols[p * kMaxPivot];
-  const int lrow = lane & 31, lcol = lane >> 5;
-  size_t coff[8];
-  unsigned okbits = 0;
+  // loader: instruction j of wave w fills columns 4 (kGramIpwC w + j) .. + 3;
+  // this lane, column col, fetches row (lane % 16) ^ (col % 16) of each block
+  const dv2* colp[kGramIpwC];
+  int lrow[kGramIpwC];
 #pragma unroll
-  for (int i = 0; i < 8; i++) {
-    const int c = 2 * (wave + 4 * i) + lcol;
-    const int pc = c < m ? cols[p * kMaxPivot + c] : -1;
-    okbits |= pc >= 0 ? (1u << i) : 0u;
-    coff[i] = (size_t)(pc >= 0 ? pc : c0) * ldg;
+  for (int j = 0; j < kGramIpwC; j++) {
+    const int col = 4 * (kGramIpwC * wave + j) + lane / 16;
+    lrow[j] = (lane & 15) ^ (col & 15);
+    colp[j] = col < m ? reinterpret_cast<const dv2*>(Gm) + (size_t)cols[p * kMaxPivot + col] * ldg : nullptr;
   }
-  dv2 ld[8];
-  auto load_block = [&](int b) {
-    const int row = r0 + b * kGramRowsC + lrow;
-    const unsigned ok = row < r1 ? okbits : 0u;
-    const int rl = min(row, r1 - 1);
+  auto issue = [&](int b, int buf) {
+    dv2* S = smem + buf * (kMaxPivot * kGramRowsC);
 #pragma unroll
-    for (int i = 0; i < 8; i++) ld[i] = G[coff[i] + rl] * ((ok >> i) & 1u ? 1.0 : 0.0);
-  };
-  auto store_block = [&](int buf) {
-    dv2* S = smem + buf * (kMaxPivot * kGramLdcC);
-#pragma unroll
-    for (int i = 0; i < 8; i++) S[(2 * (wave + 4 * i) + lcol) * kGramLdcC + lrow] = ld[i];
+    for (int j = 0; j < kGramIpwC; j++) {
+      const int row = r0 + b * kGramRowsC + lrow[j];
+      const void* src = (colp[j] != nullptr && row < r1) ? (const void*)(colp[j] + row) : (const void*)gram_zero_pair;
+      __builtin_amdgcn_global_load_lds(src, (lds_void)(S + (kGramIpwC * wave + j) * (4 * kGramRowsC)), 16, 0, 0);
+    }
   };
 
   const int hh = wave >> 1, ts = wave & 1;
@@ -427,21 +468,31 @@ __device__ __forceinline__ void gram_cplx_body(const double* __restrict__ G0, in
     a2[u] = GAcc<F32>::zero();
     a3[u] = GAcc<F32>::zero();
   }
-  load_block(0);
-  store_block(0);
-  __syncthreads();
+  for (int b = 0; b < kGramBufsC - 1 && b < nblk; b++) issue(b, b);
   // full: all four column tiles in use, no branch around the MFMAs
   auto rows = [&](auto full) {
+    int buf = 0;
     for (int b = 0; b < nblk; b++) {
-      if (b + 1 < nblk) load_block(b + 1);  // in flight during the MFMAs below
-      const dv2* S = smem + (b & 1) * (kMaxPivot * kGramLdcC);
+      // this wave's loads of block b have landed once at most the later
+      // blocks' are in flight; then a bare barrier (no release fence, which
+      // would wait for every load in flight)
+      const int later = min(kGramBufsC - 2, nblk - 1 - b);  // blocks issued after b
+      if (later >= 2) JJ_WAIT_VM(2 * kGramIpwC);
+      else if (later == 1) JJ_WAIT_VM(kGramIpwC);
+      else JJ_WAIT_VM(0);
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_s_barrier();
+      asm volatile("" ::: "memory");
+      // the buffer of block b - 1, free since the barrier above
+      if (b + kGramBufsC - 1 < nblk) issue(b + kGramBufsC - 1, buf == 0 ? kGramBufsC - 1 : buf - 1);
+      const dv2* S = smem + buf * (kMaxPivot * kGramRowsC);
 #pragma unroll
-      for (int kk = 0; kk < 4; kk++) {
-        const int row = 16 * hh + 4 * kk + g;
+      for (int kk = 0; kk < kGramRowsC / 8; kk++) {
+        const int r = (kGramRowsC / 2) * hh + 4 * kk + g;
         double xr[4], xi[4];
 #pragma unroll
         for (int T = 0; T < 4; T++) {
-          const dv2 v = S[(16 * T + c16) * kGramLdcC + row];
+          const dv2 v = S[(16 * T + c16) * kGramRowsC + (r ^ c16)];
           xr[T] = v.x;
           xi[T] = v.y;
         }
@@ -450,14 +501,14 @@ __device__ __forceinline__ void gram_cplx_body(const double* __restrict__ G0, in
         else
           gram3m_tiles<1, decltype(full)::value, F32>(xr, xi, nt, a1, a2, a3);
       }
-      if (b + 1 < nblk) store_block((b + 1) & 1);
-      __syncthreads();
+      buf = buf == kGramBufsC - 1 ? 0 : buf + 1;
     }
   };
   if (nt == 4)
     rows(std::true_type{});
   else
     rows(std::false_type{});
+  __syncthreads();  // every wave is done with the blocks: the reduction reuses them
   // fixed-order reduction of the two row halves through LDS, in FP64: half 0 + half 1
   d4 q1[5], q2[5], q3[5];
 #pragma unroll
@@ -495,7 +546,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_cplx(const double* __restrict__
                                                      const int* __restrict__ cols, const int* __restrict__ mlist,
                                                      int rows_per_chunk, double* __restrict__ part, Batch bt,
                                                      const int* __restrict__ only) {
-  __shared__ dv2 smem[2 * kMaxPivot * kGramLdcC];  // two staged blocks; then the wave reduction
+  __shared__ dv2 smem[kGramSmemC];  // the staged blocks; then the wave reduction
   int slot, ch;
   xcd_slot_chunk(slot, ch);
   if (only != nullptr && !only[slot]) return;  // a re-solve launch: this pivot was solved
@@ -506,7 +557,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_cplx_sel(const double* __restri
                                                          const int* __restrict__ cols, const int* __restrict__ mlist,
                                                          int rows_per_chunk, double* __restrict__ part, Batch bt,
                                                          const int* __restrict__ f64) {
-  __shared__ dv2 smem[2 * kMaxPivot * kGramLdcC];
+  __shared__ dv2 smem[kGramSmemC];
   int slot, ch;
   xcd_slot_chunk(slot, ch);
   if (gram_slot_f64(bt, slot, f64))
