@@ -50,8 +50,10 @@ def check_parity(G, J, lam_gpu, tag=""):
     assert e_ora > 2.5e-13, "%s: GPU vs oracle %.3e > 1e-12 with a well-conditioned oracle" % (tag, e_gpu)
     # the relative perturbation bound of the Introduction is eps n kappa(A_s)
     # for A = G^* G, kappa(A_s) = kappa_s(G)^2; eps kappa_s(G) lies well inside it
-    bound = max(4 * e_ora, EPS * kappa_s(G))
-    assert e_gl <= bound, "%s: GPU vs long double %.3e > max(4 x oracle's %.3e, eps kappa_s)" % (tag, e_gl, e_ora)
+    ks = kappa_s(G)
+    bound = max(4 * e_ora, EPS * ks)
+    assert e_gl <= bound, "%s: GPU vs long double %.3e > max(4 x oracle's %.3e, eps kappa_s = %.3e)" % (
+        tag, e_gl, e_ora, EPS * ks)
     return e_gpu
 
 
