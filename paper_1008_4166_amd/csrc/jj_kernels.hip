@@ -82,8 +82,9 @@ __device__ __forceinline__ void atomic_max_nonneg(unsigned long long* addr, doub
 // over rows 8w..8w+7 of every block; the four waves are reduced through LDS in
 // a fixed order and the partial is written per chunk.  Measured at n = 4096
 // (64 pairs of 64 columns, 8 chunks): 34.1 -> 28.9 us per launch against
-// staging the blocks through registers; more blocks in flight (4 to 7) were
-// slower.
+// staging the blocks through registers.  Slower: three to seven blocks in
+// flight, 512-thread workgroups, and each wave fetching only its own rows
+// into an LDS region of its own (no barrier in the loop).
 // ---------------------------------------------------------------------------
 constexpr int kGramRows = 32;                        // rows per staged block
 constexpr int kGramBufs = 3;                         // staged blocks
