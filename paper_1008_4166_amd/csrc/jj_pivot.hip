@@ -438,7 +438,38 @@ __global__ __launch_bounds__(64 * LPS) __attribute__((amdgpu_waves_per_eu(DENSE 
   // Thread u of each 256-element tile takes element (u / 16, u % 16) of it; the
   // chunk loads of EB tiles are issued together, then summed in chunk order.
   const T* P = reinterpret_cast<const T*>(part) + (size_t)bslot * nch * (kMaxPivot * kMaxPivot);
-  {
+  if constexpr (!CPLX && NT == 512) {
+    // real, 512 threads: two adjacent columns of a tile row per thread (16-byte
+    // loads, half the load instructions), the same sums in the same order
+    constexpr int EB2 = 3;  // 3 x 512 threads >= 1280 column pairs of the ten upper tiles
+    const double2* P2 = reinterpret_cast<const double2*>(P);
+    double2 v[EB2][kMaxChunks];
+    int rr[EB2], cc[EB2];
+#pragma unroll
+    for (int h = 0; h < EB2; h++) {
+      const int u = tid + h * NT, t = u >> 7, w = u & 127;
+      const int I = t < 4 ? 0 : (t < 7 ? 1 : (t < 9 ? 2 : 3));
+      const int J = t - (I == 0 ? 0 : (I == 1 ? 3 : (I == 2 ? 5 : 6)));
+      const int r = 16 * I + (w >> 3), c = 16 * J + 2 * (w & 7);
+      const bool ok = t < 10 && r < m && c < m;
+      rr[h] = ok ? r : -1;
+      cc[h] = c;
+#pragma unroll
+      for (int k = 0; k < kMaxChunks; k++)
+        v[h][k] = (ok && k < nchp) ? P2[((size_t)k * (kMaxPivot * kMaxPivot) + r * kMaxPivot + c) >> 1]
+                                   : double2{0.0, 0.0};
+    }
+#pragma unroll
+    for (int h = 0; h < EB2; h++) {
+      if (rr[h] >= 0) {
+        double2 sum = v[h][0];
+#pragma unroll
+        for (int k = 1; k < kMaxChunks; k++) sum = lin2(1.0, sum, 1.0, v[h][k]);
+        R[cc[h] * LDR + rr[h]] = sum.x;
+        if (cc[h] + 1 < m) R[(cc[h] + 1) * LDR + rr[h]] = sum.y;
+      }
+    }
+  } else {
     constexpr int EB = 5;  // all loads of the partials in flight at once
     for (int u0 = tid; u0 < 10 * 256; u0 += EB * NT) {
       T v[EB][kMaxChunks];
