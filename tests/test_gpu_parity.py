@@ -374,6 +374,33 @@ def test_leading_dimensions_and_padding(cplx):
     assert np.array_equal(Vp[:, :n].cpu().numpy().T, Vref)
 
 
+@pytest.mark.parametrize("case", range(12))
+def test_random_shapes_padded(case):
+    # seeded random n (odd and even, several row chunks and a ragged last block),
+    # real or complex, block width 16 or 32, and a leading dimension ldg > n whose
+    # padding rows hold NaN: element-wise parity with the oracle, status 0
+    jj = _lib()
+    rng = np.random.default_rng(4242 + case)
+    n = int(rng.integers(65, 321))
+    cplx = bool(case % 2)
+    bw = 16 if case % 4 >= 2 else 32
+    ldg = n + int(rng.integers(1, 4))
+    G, J, _ = jjgen.make(n, cplx, int(rng.integers(0, n + 1)), float(10.0 ** rng.uniform(-8, -2)), 1.0,
+                         seed=6100 + case)
+    dt = torch.complex128 if cplx else torch.float64
+    Gp = torch.full((n, ldg), float("nan"), dtype=dt, device="cuda")  # row c = column c of G, padded
+    Gp[:, :n] = torch.from_numpy(np.ascontiguousarray(G.T)).cuda()
+    lam = torch.empty(n, dtype=torch.float64, device="cuda")
+    V = torch.empty((n, n), dtype=dt, device="cuda")
+    o = jj.make_opts(stream=torch.cuda.current_stream().cuda_stream, block_width=bw)
+    info = jj.jj_info()
+    st = jj.jjacobi_solve_ex(1 if cplx else 0, Gp.data_ptr(), J, n, ldg, lam.data_ptr(), V.data_ptr(), n,
+                             0.0, 0, o, info)
+    torch.cuda.synchronize()
+    assert st == 0, (n, cplx, bw, ldg)
+    check_parity(G, J, lam.cpu().numpy(), "random n=%d cplx=%d bw=%d ldg=%d" % (n, cplx, bw, ldg))
+
+
 @pytest.mark.parametrize("cplx", [False, True])
 @pytest.mark.parametrize("n", [130, 300, 512])
 def test_three_level_pivots(cplx, n):
